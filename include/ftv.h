@@ -1,0 +1,300 @@
+/*
+ * ftv.h -- C ABI of the MI355X (gfx950) heterogeneity-aware majority voter.
+ *
+ * The voter of Kicherer & Karl, "Heterogeneity-aware Fault Tolerance using a
+ * Self-Organizing Runtime System": after a task has been run more than once
+ * (dual-modular redundancy and its k-replica generalisation, Sec. IV-D), the
+ * voter compares the replicas' results and determines the presumable correct
+ * result.  Values of integer type are compared bit-wise; floating-point values
+ * are equal when they differ by no more than a programmer-set maximum, because
+ * diverse kernels on diverse processing units order and round differently
+ * (Sec. IV-D; the paper uses a delta of 0.1% for single precision).  The type a
+ * buffer is registered with selects its compare method (Sec. IV-E).  The voter
+ * is itself an ordinary task that can run on any device (Sec. IV-D), here one
+ * MI355X.
+ *
+ * Conventions for every call:
+ *  - Buffer pointers are DEVICE pointers unless the parameter says "host".
+ *    The caller owns all buffers; the library owns only its context workspace
+ *    and, for the server, the output buffers it hands out until ftv_release.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls enqueue work and return; outputs are valid once the stream has
+ *    been synchronised.  Inputs must stay alive and unchanged until then.
+ *  - Return value: FTV_OK (0) or a negative FTV_E_* code.  No call throws or
+ *    aborts.  ftv_last_error() returns a thread-local description of the last
+ *    failure on the calling thread.
+ *  - A context is used by one host thread at a time, and calls that share a
+ *    context must be ordered on one stream (they share its workspace).  The
+ *    server calls (ftv_submit / ftv_poll / ftv_release / ftv_server_get_stats) are
+ *    thread-safe.
+ */
+#ifndef FTV_H
+#define FTV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define FTV_OK 0
+#define FTV_E_INVALID (-1)  /* bad argument (NULL pointer, size, tolerance) */
+#define FTV_E_DTYPE (-2)    /* unknown value type, or tolerance illegal for it */
+#define FTV_E_K (-3)        /* replica count outside [2, FTV_MAX_K] */
+#define FTV_E_ALIGN (-4)    /* pointer misaligned for the requested call */
+#define FTV_E_HIP (-5)      /* a HIP runtime call failed (text in ftv_last_error) */
+#define FTV_E_NOMEM (-6)    /* allocation failed, or request exceeds the budget */
+#define FTV_E_BUSY (-7)     /* server queue full */
+#define FTV_E_NOTREADY (-8) /* ftv_poll: request still in flight */
+#define FTV_E_CLOSED (-9)   /* server shutting down / unknown ticket */
+
+/* ---- value types (Sec. IV-E: registration carries the value type) --------- */
+#define FTV_F32 0
+#define FTV_F64 1
+#define FTV_I32 2
+#define FTV_I64 3
+
+/* ---- tolerance kinds (Sec. IV-D) ------------------------------------------ */
+#define FTV_TOL_EXACT 0 /* bit-wise; the only kind for integer types */
+#define FTV_TOL_ULP 1   /* |key(a) - key(b)| <= max_ulp, key = signed-magnitude
+                           bits as two's complement (+0 and -0 both 0) */
+#define FTV_TOL_REL 2   /* |a-b| <= delta*max(|a|,|b|) or |a-b| <= abs_floor,
+                           evaluated in IEEE binary64, round-to-nearest-even,
+                           no fused multiply-add, no flush-to-zero */
+
+/* ---- verdicts ------------------------------------------------------------- */
+#define FTV_UNANIMOUS 0        /* every pair of replicas agrees everywhere */
+#define FTV_TASK_MAJORITY 1    /* replica `winner` agrees with a strict majority
+                                  of the replicas over the whole task */
+#define FTV_ELEMENT_MAJORITY 2 /* every element has a strict majority; only the
+                                  consensus buffer is a valid result */
+#define FTV_UNRESOLVED 3       /* some element has no majority: re-execute */
+
+#define FTV_MAX_K 7
+#define FTV_MASK_NOMAJ 0x80 /* mask bit 7: element without a strict majority */
+
+/* Tolerance.  NaN equals any NaN; an infinity equals only the same infinity;
+ * +0 equals -0 (ULP and REL).  EXACT compares bit patterns. */
+typedef struct ftv_tol {
+  int32_t kind;      /* FTV_TOL_* */
+  uint32_t reserved; /* must be 0 */
+  uint64_t max_ulp;  /* FTV_TOL_ULP */
+  double delta;      /* FTV_TOL_REL, e.g. 1e-3 for the paper's 0.1% */
+  double abs_floor;  /* FTV_TOL_REL, 0 for none */
+} ftv_tol;
+
+/* Per-task result of a vote (device memory, written whole by the library). */
+typedef struct ftv_stats {
+  uint64_t pair[FTV_MAX_K][FTV_MAX_K]; /* elements where replicas i, j are unequal;
+                                          symmetric, zero diagonal, zero beyond k */
+  uint64_t disagree[FTV_MAX_K];        /* elements where replica r != consensus */
+  uint64_t no_majority;                /* elements without a strict majority */
+  uint64_t n;                          /* elements voted */
+  int32_t verdict;                     /* FTV_UNANIMOUS .. FTV_UNRESOLVED */
+  int32_t winner;                      /* TASK_MAJORITY: lowest replica agreeing with
+                                          the most replicas over the whole task;
+                                          otherwise the replica with the fewest
+                                          disagreements (lowest index on ties) */
+} ftv_stats;
+
+/* One vote task: k replicas of n elements of one value type. */
+typedef struct ftv_vote_desc {
+  const void *replicas[FTV_MAX_K]; /* k device buffers, element-aligned */
+  uint32_t k;                      /* 2..FTV_MAX_K */
+  int32_t dtype;                   /* FTV_F32 .. FTV_I64 */
+  uint64_t n;                      /* elements per replica (0 allowed) */
+  ftv_tol tol;
+  void *consensus;   /* n elements, or NULL (not written) */
+  uint8_t *mask;     /* n bytes, or NULL: bit r = replica r unequal to the
+                        consensus, bit 7 = no strict majority */
+  ftv_stats *stats;  /* required */
+} ftv_vote_desc;
+
+typedef struct ftv_ctx ftv_ctx;
+
+/* Library version string (static). */
+const char *ftv_version(void);
+/* Description of the last failure on this thread ("" if none). */
+const char *ftv_last_error(void);
+/* Monotonic clock used for all server timestamps (ns). */
+int64_t ftv_now_ns(void);
+
+/* Create a context on HIP device `device`: allocates its workspace (a few MiB).
+ * *out receives the handle.  Errors: FTV_E_INVALID, FTV_E_HIP, FTV_E_NOMEM. */
+int ftv_ctx_create(int device, ftv_ctx **out);
+/* Waits for nothing: the caller must synchronise its streams first. */
+int ftv_ctx_destroy(ftv_ctx *ctx);
+
+/* ftv_vote -- the element-wise majority vote of one task (Sec. IV-D).
+ *
+ * Per element i, with eq() the tolerance test:
+ *   support s_r = #{j : eq(x_r, x_j)} (itself included), M = max_r s_r;
+ *   the element has a majority iff 2M > k;
+ *   the consensus is, among the replicas of support M, the lower median under
+ *   IEEE-754 totalOrder of the raw bits (two's-complement order for integers);
+ *   mask bit r = !eq(x_r, consensus), bit 7 = no majority.
+ * Counts: pair[i][j] = #(!eq(x_i, x_j)), disagree[r] = #(mask bit r),
+ * no_majority = #(mask bit 7).  Verdict from those counts (see FTV_* above).
+ * Results are bit-exact functions of the inputs: no launch shape, tile size or
+ * schedule changes them.
+ * Errors: FTV_E_INVALID (NULL replica/stats, reserved != 0, bad tolerance),
+ * FTV_E_DTYPE, FTV_E_K, FTV_E_ALIGN (pointer not a multiple of the element
+ * size; stats not 8-byte aligned), FTV_E_HIP. */
+int ftv_vote(ftv_ctx *ctx, const ftv_vote_desc *desc, void *stream);
+
+/* ftv_vote_batch -- ntasks independent votes (any mix of value types, k and
+ * tolerances) in ONE persistent kernel launch, replayed from a captured HIP
+ * graph.  `descs` is a HOST array.  Each task's results are identical to those
+ * of ftv_vote on the same task.  Additional requirement: every replica and
+ * consensus pointer 16-byte aligned and every mask pointer 4-byte aligned
+ * (FTV_E_ALIGN otherwise).  The host arrays may be reused as soon as the call
+ * returns. */
+int ftv_vote_batch(ftv_ctx *ctx, const ftv_vote_desc *descs, uint64_t ntasks, void *stream);
+
+/* Schedule of the batched launch, chosen by ftv_tune_batch.  None of these
+ * fields can change a result, only the time taken. */
+typedef struct ftv_batch_cfg {
+  uint32_t tile_vecs;  /* 16-byte vectors per replica per tile (multiple of block) */
+  uint32_t block;      /* threads per workgroup: 256 or 512 */
+  uint32_t grid_mult;  /* workgroups per compute unit */
+  uint32_t order;      /* 0 = task order, 1 = largest task first (LPT),
+                          2 = tiles interleaved round-robin across tasks */
+  uint32_t nt_stores;  /* 1 = non-temporal stores for consensus and mask */
+  uint32_t reserved;
+} ftv_batch_cfg;
+
+int ftv_batch_get_config(ftv_ctx *ctx, ftv_batch_cfg *out);
+/* FTV_E_INVALID if a field is out of range. */
+int ftv_batch_set_config(ftv_ctx *ctx, const ftv_batch_cfg *cfg);
+/* Autotuner: times every candidate schedule on this batch (`iters` timed runs
+ * each, on `stream`, synchronising it), installs the fastest in the context and
+ * writes it to *best (may be NULL).  The batch's outputs hold a valid result
+ * afterwards.  If the environment variable FTV_TUNE_CACHE names a file, the
+ * choice is stored there as JSON keyed by device name, CU count and a coarse
+ * signature of the batch, and reused by ftv_tune_batch on a cache hit. */
+int ftv_tune_batch(ftv_ctx *ctx, const ftv_vote_desc *descs, uint64_t ntasks, void *stream,
+                   uint32_t iters, ftv_batch_cfg *best);
+
+/* ftv_fingerprint -- one 64-bit fingerprint per block of `block_bytes` of a
+ * buffer, for validating checkpoints (the paper validates by versioned backup
+ * copies, Sec. IV-A/IV-C; the fingerprint makes a copy comparable without
+ * moving it).  Definition: the buffer is read as little-endian 64-bit words,
+ * zero-padded to whole blocks; a leaf is 64-bit FNV-1a over 8 words (64 B);
+ * leaves are combined pairwise, (0,1), (2,3), ..., level by level, a node being
+ * FNV-1a over the two words (left, right).
+ * block_bytes: a power of two in [4096, 65536].  buf: 16-byte aligned.
+ * fp_out: ceil(nbytes / block_bytes) uint64 (device).
+ * Errors: FTV_E_INVALID, FTV_E_ALIGN, FTV_E_HIP. */
+int ftv_fingerprint(ftv_ctx *ctx, const void *buf, uint64_t nbytes, uint64_t block_bytes,
+                    uint64_t *fp_out, void *stream);
+
+/* Result of a block vote (device memory, written whole). */
+typedef struct ftv_block_stats {
+  uint64_t blocks;              /* ceil(nbytes / block_bytes) */
+  uint64_t disagree_blocks;     /* blocks where some fingerprint differs */
+  uint64_t fallback_blocks;     /* blocks without a fingerprint majority */
+  uint64_t unresolved_elems;    /* elements of fallback blocks without majority */
+  uint64_t replica_blocks[FTV_MAX_K]; /* blocks where replica r differs from the source */
+  int32_t verdict;              /* UNANIMOUS: no block differs; TASK_MAJORITY:
+                                   no fallback and replica `winner` matches the
+                                   source everywhere; ELEMENT_MAJORITY: every
+                                   element resolved; else UNRESOLVED */
+  int32_t winner;
+} ftv_block_stats;
+
+/* ftv_vote_blocks -- checkpoint validation plus vote: fingerprints every block
+ * of the k replicas, votes the fingerprints by exact equality, and restores the
+ * consensus by copying, per block, the block of the lowest-indexed replica that
+ * holds a strict-majority fingerprint (recopy from a valid copy, Sec. IV-A).  A
+ * block without a fingerprint majority falls back to the element vote of
+ * ftv_vote under `fallback_tol` over that block's elements.
+ * replicas: HOST array of k device pointers, each 16-byte aligned.
+ * nbytes: a multiple of the element size.  block_bytes: power of two in
+ * [4096, 65536].  fps: k * nblocks uint64 (replica-major) or NULL.
+ * blockmap: nblocks bytes: bit r = replica r's fingerprint differs from the
+ * source's, bit 7 = no fingerprint majority.  consensus: nbytes.  mask: n bytes
+ * or NULL; 0 outside fallback blocks, element-vote mask inside them. */
+int ftv_vote_blocks(ftv_ctx *ctx, const void *const *replicas, uint32_t k, int32_t dtype,
+                    uint64_t nbytes, uint64_t block_bytes, const ftv_tol *fallback_tol,
+                    uint64_t *fps, uint8_t *blockmap, void *consensus, uint8_t *mask,
+                    ftv_block_stats *bstats, void *stream);
+
+/* ---- serving: continuous batching of vote / fingerprint requests ---------- *
+ * The voter as a service that admits requests as tasks finish (Sec. IV-D: the
+ * voter is a task the runtime schedules like any other).  A server thread admits
+ * queued requests in arrival order while the HBM budget and the slot count
+ * allow, and runs iterations: each iteration is one persistent launch over a
+ * chunk (<= chunk_bytes per replica) of every admitted request, so requests
+ * that arrive while others are on the GPU join the next iteration and their
+ * work shares launches.  Results are identical to ftv_vote / ftv_fingerprint of
+ * the same request alone. */
+typedef struct ftv_server ftv_server;
+
+typedef struct ftv_server_cfg {
+  uint64_t hbm_budget_bytes; /* admitted footprint limit (inputs + outputs) */
+  uint32_t max_slots;        /* requests admitted at once, <= 4096 */
+  uint32_t max_queue;        /* queued (not yet admitted) requests; submit
+                                returns FTV_E_BUSY beyond it */
+  uint64_t chunk_bytes;      /* per-request bytes per replica per iteration */
+  int32_t device;
+  uint32_t reserved;
+} ftv_server_cfg;
+
+#define FTV_REQ_VOTE 0
+#define FTV_REQ_FINGERPRINT 1
+
+typedef struct ftv_request {
+  int32_t kind;        /* FTV_REQ_VOTE or FTV_REQ_FINGERPRINT */
+  uint32_t reserved;
+  ftv_vote_desc vote;  /* VOTE: replicas/k/dtype/n/tol; consensus and mask may be
+                          caller buffers or NULL = allocated by the server from
+                          its budget; stats is ignored (the result carries them).
+                          Same alignment rules as ftv_vote_batch. */
+  const void *fp_buf;  /* FINGERPRINT: 16-byte aligned device buffer */
+  uint64_t fp_bytes;
+  uint64_t block_bytes;
+  int64_t t_arrival_ns; /* ftv_now_ns() clock; 0 = time of submission */
+  uint64_t user_tag;
+} ftv_request;
+
+typedef struct ftv_result {
+  int32_t status;      /* FTV_OK or the error that ended the request */
+  int32_t kind;
+  ftv_stats stats;     /* host copy (VOTE) */
+  void *consensus;     /* device; server-owned until ftv_release if allocated */
+  uint8_t *mask;
+  uint64_t *fps;       /* FINGERPRINT: device, server-owned until ftv_release */
+  uint64_t nfps;
+  int64_t t_arrival_ns, t_submit_ns, t_admit_ns, t_done_ns;
+  uint64_t user_tag;
+} ftv_result;
+
+typedef struct ftv_server_stats {
+  uint64_t submitted, completed, queued, in_flight, rejected;
+  uint64_t bytes_in_flight, peak_bytes_in_flight;
+  uint64_t iterations, peak_queue_depth;
+  double mean_queue_depth;   /* time-averaged queued requests */
+  double p50_us, p99_us;     /* arrival -> completion, completed requests */
+  double mean_us, max_us;
+  double replica_gbps;       /* replica bytes voted / busy wall time */
+} ftv_server_stats;
+
+int ftv_server_create(const ftv_server_cfg *cfg, ftv_server **out);
+/* Enqueue a request; *ticket identifies it.  FTV_E_NOMEM if its footprint
+ * alone exceeds the budget, FTV_E_BUSY if the queue is full. */
+int ftv_submit(ftv_server *srv, const ftv_request *req, uint64_t *ticket);
+/* Wait up to wait_us (0 = do not wait, <0 = forever) for a ticket.
+ * FTV_OK with *out filled, FTV_E_NOTREADY, or FTV_E_CLOSED (unknown ticket). */
+int ftv_poll(ftv_server *srv, uint64_t ticket, ftv_result *out, int64_t wait_us);
+/* Forget a completed ticket and return its server-allocated outputs to the
+ * budget. */
+int ftv_release(ftv_server *srv, uint64_t ticket);
+int ftv_server_get_stats(ftv_server *srv, ftv_server_stats *out);
+/* Drains in-flight work, then stops the server thread and frees everything. */
+int ftv_server_destroy(ftv_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FTV_H */

@@ -1,0 +1,613 @@
+// ftv_api.cpp -- C ABI entry points: context, validation, per-task vote,
+// batched vote (table build, HIP graph replay) and its autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <ctime>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ftv.h"
+#include "ftv_common.hpp"
+#include "ftv_internal.hpp"
+
+namespace ftv {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();  // clear the sticky launch error, if any
+  return FTV_E_HIP;
+}
+
+int elem_size(int dtype) { return (dtype == FTV_F32 || dtype == FTV_I32) ? 4 : 8; }
+
+static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+int check_tol(int dtype, const ftv_tol &t) {
+  if (dtype < FTV_F32 || dtype > FTV_I64) return fail(FTV_E_DTYPE, "unknown dtype");
+  if (t.reserved != 0) return fail(FTV_E_INVALID, "tol.reserved must be 0");
+  if (t.kind < FTV_TOL_EXACT || t.kind > FTV_TOL_REL) return fail(FTV_E_INVALID, "unknown tolerance kind");
+  const bool fl = dtype == FTV_F32 || dtype == FTV_F64;
+  if (!fl && t.kind != FTV_TOL_EXACT)
+    return fail(FTV_E_DTYPE, "integer types are compared bit-wise (FTV_TOL_EXACT only)");
+  if (t.kind == FTV_TOL_REL && (!(t.delta >= 0.0) || !(t.abs_floor >= 0.0)))
+    return fail(FTV_E_INVALID, "REL tolerance needs delta >= 0 and abs_floor >= 0");
+  return FTV_OK;
+}
+
+TolD to_tol_d(int dtype, const ftv_tol &t) {
+  TolD d;
+  d.max_ulp = t.max_ulp;
+  if (elem_size(dtype) == 4 && d.max_ulp > 0xffffffffull) d.max_ulp = 0xffffffffull;
+  d.delta = t.delta;
+  d.abs_floor = t.abs_floor;
+  return d;
+}
+
+// Validate a vote descriptor and fill the device task record.  strict = batch
+// alignment rules (16-byte replicas/consensus, 4-byte mask).
+int make_task(const ftv_vote_desc *d, bool strict, TaskD *out) {
+  if (!d) return fail(FTV_E_INVALID, "NULL descriptor");
+  if (d->k < 2 || d->k > FTV_MAX_K) return fail(FTV_E_K, "k must be in [2, 7]");
+  int rc = check_tol(d->dtype, d->tol);
+  if (rc) return rc;
+  if (!d->stats) return fail(FTV_E_INVALID, "stats pointer is NULL");
+  if (!aligned(d->stats, 8)) return fail(FTV_E_ALIGN, "stats must be 8-byte aligned");
+  const int es = elem_size(d->dtype);
+  bool vec = true;
+  for (uint32_t r = 0; r < d->k; ++r) {
+    if (!d->replicas[r] && d->n) return fail(FTV_E_INVALID, "replica pointer is NULL");
+    if (!aligned(d->replicas[r], es)) return fail(FTV_E_ALIGN, "replica not element-aligned");
+    vec = vec && aligned(d->replicas[r], 16);
+  }
+  if (d->consensus) {
+    if (!aligned(d->consensus, es)) return fail(FTV_E_ALIGN, "consensus not element-aligned");
+    vec = vec && aligned(d->consensus, 16);
+  }
+  if (d->mask) vec = vec && aligned(d->mask, 4);
+  if (strict && !vec)
+    return fail(FTV_E_ALIGN, "batched tasks need 16-byte aligned replicas/consensus, 4-byte mask");
+  memset(out, 0, sizeof(*out));
+  for (uint32_t r = 0; r < d->k; ++r) out->rep[r] = d->replicas[r];
+  out->cons = d->consensus;
+  out->mask = d->mask;
+  out->stats = d->stats;
+  out->n = d->n;
+  out->vec = vec ? 1u : 0u;
+  out->nvec = vec ? d->n / (uint64_t)(16 / es) : d->n;
+  out->tol = to_tol_d(d->dtype, d->tol);
+  out->k = d->k;
+  out->spec = spec_code(d->dtype, d->tol.kind, (int)d->k);
+  out->ntiles = 1;
+  return FTV_OK;
+}
+
+}  // namespace ftv
+
+using namespace ftv;
+
+// ---------------------------------------------------------------------------
+struct ftv_ctx {
+  int device = 0;
+  int num_cus = 256;
+  std::string name;
+  // per-task launch workspace
+  uint64_t *partials = nullptr;
+  uint32_t *ticket = nullptr;
+  // batched launch
+  ftv_batch_cfg cfg{};
+  uint64_t cap_tasks = 0, cap_tiles = 0;
+  char *d_tab = nullptr;   // [hdr 256 B][TaskD x cap_tasks][TileD x cap_tiles]
+  char *h_tab = nullptr;   // pinned staging of the same layout
+  uint64_t *d_acc = nullptr;
+  uint32_t *d_done = nullptr;
+  uint32_t *d_queue = nullptr;
+  hipEvent_t staged{};
+  bool staged_pending = false;
+  hipStream_t cap_stream{};
+  hipGraphExec_t gexec{};
+  hipGraph_t graph{};
+  bool gvalid = false;
+  uint32_t g_grid = 0;
+  ftv_batch_cfg g_cfg{};
+  // block vote workspace
+  uint64_t *blk_acc = nullptr;
+  uint32_t *blk_ticket = nullptr;
+};
+
+namespace {
+
+const ftv_batch_cfg kDefaultCfg = {4096u, 256u, 3u, 1u, 1u, 0u};
+
+int cfg_check(const ftv_batch_cfg &c) {
+  if (c.block != 256 && c.block != 512) return fail(FTV_E_INVALID, "block must be 256 or 512");
+  if (c.tile_vecs < 256 || c.tile_vecs > (1u << 22)) return fail(FTV_E_INVALID, "tile_vecs out of range");
+  if (c.grid_mult < 1 || c.grid_mult > 32) return fail(FTV_E_INVALID, "grid_mult out of range");
+  if (c.order > 2 || c.nt_stores > 1 || c.reserved != 0) return fail(FTV_E_INVALID, "bad order/nt_stores");
+  return FTV_OK;
+}
+
+size_t tab_bytes(uint64_t tasks, uint64_t tiles) {
+  return 256 + sizeof(TaskD) * tasks + sizeof(TileD) * tiles;
+}
+
+void free_batch(ftv_ctx *c) {
+  if (c->gvalid) {
+    (void)hipGraphExecDestroy(c->gexec);
+    (void)hipGraphDestroy(c->graph);
+    c->gvalid = false;
+  }
+  if (c->d_tab) (void)hipFree(c->d_tab);
+  if (c->h_tab) (void)hipHostFree(c->h_tab);
+  if (c->d_acc) (void)hipFree(c->d_acc);
+  if (c->d_done) (void)hipFree(c->d_done);
+  c->d_tab = nullptr;
+  c->h_tab = nullptr;
+  c->d_acc = nullptr;
+  c->d_done = nullptr;
+  c->cap_tasks = c->cap_tiles = 0;
+}
+
+int ensure_capacity(ftv_ctx *c, uint64_t tasks, uint64_t tiles, hipStream_t s) {
+  if (tasks <= c->cap_tasks && tiles <= c->cap_tiles) return FTV_OK;
+  // the old buffers may still be read by queued work
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipDeviceSynchronize());
+  free_batch(c);
+  uint64_t nt = std::max<uint64_t>(tasks + tasks / 2, 1024);
+  uint64_t nl = std::max<uint64_t>(tiles + tiles / 2, 16384);
+  const size_t tb = tab_bytes(nt, nl);
+  if (hipMalloc(&c->d_tab, tb) != hipSuccess || hipHostMalloc(&c->h_tab, tb) != hipSuccess ||
+      hipMalloc(&c->d_acc, sizeof(uint64_t) * kNumCounters * nt) != hipSuccess ||
+      hipMalloc(&c->d_done, sizeof(uint32_t) * nt) != hipSuccess) {
+    (void)hipGetLastError();
+    free_batch(c);
+    return fail(FTV_E_NOMEM, "cannot allocate the batch tables");
+  }
+  c->cap_tasks = nt;
+  c->cap_tiles = nl;
+  return FTV_OK;
+}
+
+BatchLaunch make_launch(ftv_ctx *c, uint32_t grid) {
+  BatchLaunch b;
+  b.tasks = reinterpret_cast<const TaskD *>(c->d_tab + 256);
+  b.tiles = reinterpret_cast<const TileD *>(c->d_tab + 256 + sizeof(TaskD) * c->cap_tasks);
+  b.ntiles_dev = reinterpret_cast<const uint64_t *>(c->d_tab);
+  b.acc = c->d_acc;
+  b.task_done = c->d_done;
+  b.queue_head = c->d_queue;
+  b.block = c->cfg.block;
+  b.grid = grid;
+  b.nt_stores = c->cfg.nt_stores;
+  return b;
+}
+
+// Capture zero + persistent kernels once per (capacity, grid, cfg); the
+// kernels read the task and tile counts from the table header, so a new batch
+// only needs a new table upload.
+int ensure_graph(ftv_ctx *c, uint32_t grid) {
+  if (c->gvalid && c->g_grid == grid && !memcmp(&c->g_cfg, &c->cfg, sizeof(c->cfg))) return FTV_OK;
+  if (c->gvalid) {
+    (void)hipGraphExecDestroy(c->gexec);
+    (void)hipGraphDestroy(c->graph);
+    c->gvalid = false;
+  }
+  const BatchLaunch b = make_launch(c, grid);
+  HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e1 = launch_batch_zero(b, c->cap_stream);
+  hipError_t e2 = launch_batch_vote(b, c->cap_stream);
+  hipGraph_t g{};
+  hipError_t e3 = hipStreamEndCapture(c->cap_stream, &g);
+  if (e1 != hipSuccess) return hip_fail(e1, "capture zero kernel");
+  if (e2 != hipSuccess) return hip_fail(e2, "capture batch kernel");
+  if (e3 != hipSuccess) return hip_fail(e3, "hipStreamEndCapture");
+  hipError_t e4 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  if (e4 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e4, "hipGraphInstantiate");
+  }
+  c->graph = g;
+  c->gvalid = true;
+  c->g_grid = grid;
+  c->g_cfg = c->cfg;
+  return FTV_OK;
+}
+
+// Build the device task records and the ordered tile table in pinned staging.
+int build_tables(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStream_t s,
+                 uint64_t *ntiles_out) {
+  std::vector<TaskD> tasks(ntasks);
+  uint64_t ntiles = 0;
+  const uint64_t tv = c->cfg.tile_vecs;
+  for (uint64_t i = 0; i < ntasks; ++i) {
+    int rc = make_task(&descs[i], true, &tasks[i]);
+    if (rc) return fail(rc, "task " + std::to_string(i) + ": " + g_err);
+    const uint64_t nt = std::max<uint64_t>(1, (tasks[i].nvec + tv - 1) / tv);
+    if (nt > 0xffffffffull) return fail(FTV_E_INVALID, "task too large for one batch");
+    tasks[i].ntiles = (uint32_t)nt;
+    ntiles += nt;
+  }
+  if (ntasks > 0xffffffffull || ntiles > 0xffffffffull)
+    return fail(FTV_E_INVALID, "batch too large");
+  int rc = ensure_capacity(c, ntasks, ntiles, s);
+  if (rc) return rc;
+  if (c->staged_pending) {  // the previous upload must have left the staging
+    HIPCHK(hipEventSynchronize(c->staged));
+    c->staged_pending = false;
+  }
+  uint64_t *hdr = reinterpret_cast<uint64_t *>(c->h_tab);
+  hdr[0] = ntiles;
+  hdr[1] = ntasks;
+  TaskD *ht = reinterpret_cast<TaskD *>(c->h_tab + 256);
+  TileD *hl = reinterpret_cast<TileD *>(c->h_tab + 256 + sizeof(TaskD) * c->cap_tasks);
+  memcpy(ht, tasks.data(), sizeof(TaskD) * ntasks);
+  std::vector<uint32_t> ord(ntasks);
+  for (uint64_t i = 0; i < ntasks; ++i) ord[i] = (uint32_t)i;
+  if (c->cfg.order == 1) {
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+      return tasks[a].n * tasks[a].k * elem_size((int)(tasks[a].spec / 24)) >
+             tasks[b].n * tasks[b].k * elem_size((int)(tasks[b].spec / 24));
+    });
+  }
+  uint64_t w = 0;
+  auto put = [&](uint32_t t, uint64_t j) {
+    TileD &d = hl[w++];
+    d.task = t;
+    d.v0 = j * tv;
+    d.v1 = std::min<uint64_t>((j + 1) * tv, tasks[t].nvec);
+    if (d.v0 > d.v1) d.v0 = d.v1;
+    d.last = (j + 1 == tasks[t].ntiles) ? 1u : 0u;
+  };
+  if (c->cfg.order == 2) {
+    uint64_t maxt = 0;
+    for (auto &t : tasks) maxt = std::max<uint64_t>(maxt, t.ntiles);
+    for (uint64_t j = 0; j < maxt; ++j)
+      for (uint32_t t : ord)
+        if (j < tasks[t].ntiles) put(t, j);
+  } else {
+    for (uint32_t t : ord)
+      for (uint64_t j = 0; j < tasks[t].ntiles; ++j) put(t, j);
+  }
+  const size_t bytes = 256 + sizeof(TaskD) * c->cap_tasks + sizeof(TileD) * ntiles;
+  HIPCHK(hipMemcpyAsync(c->d_tab, c->h_tab, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(c->staged, s));
+  c->staged_pending = true;
+  *ntiles_out = ntiles;
+  return FTV_OK;
+}
+
+int batch_run(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStream_t s) {
+  if (ntasks == 0) return FTV_OK;
+  uint64_t ntiles = 0;
+  int rc = build_tables(c, descs, ntasks, s, &ntiles);
+  if (rc) return rc;
+  uint64_t grid = (uint64_t)c->cfg.grid_mult * c->num_cus;
+  grid = std::min<uint64_t>(grid, ntiles);
+  // quantise the grid so that small batches share one captured graph
+  uint32_t g = 1;
+  while (g < grid) g <<= 1;
+  g = (uint32_t)std::min<uint64_t>(g, (uint64_t)c->cfg.grid_mult * c->num_cus);
+  rc = ensure_graph(c, g);
+  if (rc) return rc;
+  HIPCHK(hipGraphLaunch(c->gexec, s));
+  return FTV_OK;
+}
+
+// ---- tune cache (flat JSON object: key -> [tile_vecs, block, grid_mult, order, nt]) ----
+std::string tune_key(ftv_ctx *c, const ftv_vote_desc *d, uint64_t n) {
+  uint64_t bytes = 0;
+  for (uint64_t i = 0; i < n; ++i) bytes += d[i].n * d[i].k * elem_size(d[i].dtype);
+  int lt = 0, lb = 0;
+  while ((1ull << lt) < n) ++lt;
+  while ((1ull << lb) < bytes) ++lb;
+  std::ostringstream o;
+  o << c->name << "|cu" << c->num_cus << "|t2^" << lt << "|b2^" << lb;
+  return o.str();
+}
+
+bool cache_lookup(const std::string &path, const std::string &key, ftv_batch_cfg *out) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string txt = ss.str();
+  const std::string pat = "\"" + key + "\": [";
+  size_t p = txt.find(pat);
+  if (p == std::string::npos) return false;
+  unsigned v[5];
+  if (sscanf(txt.c_str() + p + pat.size(), "%u, %u, %u, %u, %u", &v[0], &v[1], &v[2], &v[3], &v[4]) != 5)
+    return false;
+  ftv_batch_cfg cfg = {v[0], v[1], v[2], v[3], v[4], 0};
+  if (cfg_check(cfg) != FTV_OK) return false;
+  *out = cfg;
+  return true;
+}
+
+void cache_store(const std::string &path, const std::string &key, const ftv_batch_cfg &cfg) {
+  std::vector<std::pair<std::string, std::string>> items;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (f && std::getline(f, line)) {
+      size_t a = line.find('"'), b = line.find("\": [");
+      if (a == std::string::npos || b == std::string::npos || b <= a) continue;
+      std::string k = line.substr(a + 1, b - a - 1);
+      size_t e = line.find(']', b);
+      if (e == std::string::npos) continue;
+      if (k != key) items.emplace_back(k, line.substr(b + 4, e - b - 4));
+    }
+  }
+  std::ostringstream v;
+  v << cfg.tile_vecs << ", " << cfg.block << ", " << cfg.grid_mult << ", " << cfg.order << ", " << cfg.nt_stores;
+  items.emplace_back(key, v.str());
+  std::ofstream f(path, std::ios::trunc);
+  f << "{\n";
+  for (size_t i = 0; i < items.size(); ++i)
+    f << "  \"" << items[i].first << "\": [" << items[i].second << "]" << (i + 1 < items.size() ? "," : "") << "\n";
+  f << "}\n";
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *ftv_version(void) { return "ftv 0.1 gfx950"; }
+
+const char *ftv_last_error(void) { return g_err.c_str(); }
+
+int64_t ftv_now_ns(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
+}
+
+int ftv_ctx_create(int device, ftv_ctx **out) {
+  if (!out) return fail(FTV_E_INVALID, "NULL output handle");
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(FTV_E_INVALID, "no such device");
+  HIPCHK(hipSetDevice(device));
+  ftv_ctx *c = new (std::nothrow) ftv_ctx();
+  if (!c) return fail(FTV_E_NOMEM, "out of host memory");
+  c->device = device;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDeviceProperties");
+  }
+  c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->name = prop.gcnArchName;
+  c->cfg = kDefaultCfg;
+  bool ok = hipMalloc(&c->partials, sizeof(uint64_t) * kMaxGrid * kNumCounters) == hipSuccess &&
+            hipMalloc(&c->ticket, 256) == hipSuccess && hipMalloc(&c->d_queue, 256) == hipSuccess &&
+            hipMalloc(&c->blk_acc, 256) == hipSuccess && hipMalloc(&c->blk_ticket, 256) == hipSuccess &&
+            hipMemset(c->ticket, 0, 256) == hipSuccess && hipMemset(c->blk_ticket, 0, 256) == hipSuccess &&
+            hipMemset(c->blk_acc, 0, 256) == hipSuccess &&
+            hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess &&
+            hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    ftv_ctx_destroy(c);
+    return fail(FTV_E_NOMEM, "cannot allocate the context workspace");
+  }
+  *out = c;
+  return FTV_OK;
+}
+
+int ftv_ctx_destroy(ftv_ctx *c) {
+  if (!c) return FTV_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  free_batch(c);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->ticket) (void)hipFree(c->ticket);
+  if (c->d_queue) (void)hipFree(c->d_queue);
+  if (c->blk_acc) (void)hipFree(c->blk_acc);
+  if (c->blk_ticket) (void)hipFree(c->blk_ticket);
+  if (c->staged) (void)hipEventDestroy(c->staged);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+  return FTV_OK;
+}
+
+int ftv_vote(ftv_ctx *c, const ftv_vote_desc *desc, void *stream) {
+  if (!c) return fail(FTV_E_INVALID, "NULL context");
+  TaskD t;
+  int rc = make_task(desc, false, &t);
+  if (rc) return rc;
+  VoteWs ws{c->partials, c->ticket};
+  hipError_t e = launch_vote_task(t, ws, c->num_cus, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
+  return FTV_OK;
+}
+
+int ftv_vote_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void *stream) {
+  if (!c) return fail(FTV_E_INVALID, "NULL context");
+  if (ntasks && !descs) return fail(FTV_E_INVALID, "NULL descriptor array");
+  return batch_run(c, descs, ntasks, (hipStream_t)stream);
+}
+
+int ftv_batch_get_config(ftv_ctx *c, ftv_batch_cfg *out) {
+  if (!c || !out) return fail(FTV_E_INVALID, "NULL argument");
+  *out = c->cfg;
+  return FTV_OK;
+}
+
+int ftv_batch_set_config(ftv_ctx *c, const ftv_batch_cfg *cfg) {
+  if (!c || !cfg) return fail(FTV_E_INVALID, "NULL argument");
+  int rc = cfg_check(*cfg);
+  if (rc) return rc;
+  c->cfg = *cfg;
+  return FTV_OK;
+}
+
+int ftv_tune_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void *stream,
+                   uint32_t iters, ftv_batch_cfg *best) {
+  if (!c) return fail(FTV_E_INVALID, "NULL context");
+  if (ntasks && !descs) return fail(FTV_E_INVALID, "NULL descriptor array");
+  hipStream_t s = (hipStream_t)stream;
+  if (iters < 1) iters = 1;
+  const char *path = getenv("FTV_TUNE_CACHE");
+  const std::string key = tune_key(c, descs, ntasks);
+  ftv_batch_cfg hit;
+  if (path && *path && cache_lookup(path, key, &hit)) {
+    c->cfg = hit;
+    int rc = batch_run(c, descs, ntasks, s);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    if (best) *best = hit;
+    return FTV_OK;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto time_cfg = [&](const ftv_batch_cfg &cfg, double *ms) -> int {
+    c->cfg = cfg;
+    int rc = batch_run(c, descs, ntasks, s);  // warm: capture + first touch
+    if (rc) return rc;
+    std::vector<float> t;
+    for (uint32_t i = 0; i < iters; ++i) {
+      HIPCHK(hipEventRecord(e0, s));
+      rc = batch_run(c, descs, ntasks, s);
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms1 = 0;
+      HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
+      t.push_back(ms1);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return FTV_OK;
+  };
+  // coordinate descent from the default: one parameter at a time
+  ftv_batch_cfg cur = c->cfg;
+  double best_ms = 1e30;
+  int rc = time_cfg(cur, &best_ms);
+  const std::vector<uint32_t> tiles = {1024, 2048, 4096, 8192, 16384, 65536};
+  const std::vector<uint32_t> blocks = {256, 512};
+  const std::vector<uint32_t> grids = {1, 2, 3, 4, 8};
+  const std::vector<uint32_t> orders = {0, 1, 2};
+  const std::vector<uint32_t> nts = {0, 1};
+  for (int field = 0; field < 5 && rc == FTV_OK; ++field) {
+    const std::vector<uint32_t> &vals =
+        field == 0 ? tiles : field == 1 ? blocks : field == 2 ? grids : field == 3 ? orders : nts;
+    for (uint32_t v : vals) {
+      ftv_batch_cfg cand = cur;
+      uint32_t *f = field == 0 ? &cand.tile_vecs : field == 1 ? &cand.block
+                  : field == 2 ? &cand.grid_mult : field == 3 ? &cand.order : &cand.nt_stores;
+      if (*f == v) continue;
+      *f = v;
+      double ms = 0;
+      rc = time_cfg(cand, &ms);
+      if (rc) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        cur = cand;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  c->cfg = cur;
+  rc = batch_run(c, descs, ntasks, s);  // leave the batch's outputs from the chosen schedule
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s));
+  if (path && *path) cache_store(path, key, cur);
+  if (best) *best = cur;
+  return FTV_OK;
+}
+
+}  // extern "C"
+
+// ---- fingerprints and block vote --------------------------------------------
+namespace {
+bool pow2_in(uint64_t x, uint64_t lo, uint64_t hi) { return x >= lo && x <= hi && !(x & (x - 1)); }
+}  // namespace
+
+extern "C" {
+
+int ftv_fingerprint(ftv_ctx *c, const void *buf, uint64_t nbytes, uint64_t block_bytes,
+                    uint64_t *fp_out, void *stream) {
+  if (!c) return fail(FTV_E_INVALID, "NULL context");
+  if (!pow2_in(block_bytes, 4096, 65536))
+    return fail(FTV_E_INVALID, "block_bytes must be a power of two in [4096, 65536]");
+  if (nbytes == 0) return FTV_OK;
+  if (!buf || !fp_out) return fail(FTV_E_INVALID, "NULL buffer");
+  if ((uintptr_t)buf % 16) return fail(FTV_E_ALIGN, "buffer must be 16-byte aligned");
+  if ((uintptr_t)fp_out % 8) return fail(FTV_E_ALIGN, "fp_out must be 8-byte aligned");
+  if ((nbytes + block_bytes - 1) / block_bytes > 0x7fffffffull)
+    return fail(FTV_E_INVALID, "too many blocks for one launch");
+  hipError_t e = launch_fingerprint(buf, nbytes, block_bytes, fp_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "fingerprint kernel launch");
+  return FTV_OK;
+}
+
+int ftv_vote_blocks(ftv_ctx *c, const void *const *replicas, uint32_t k, int32_t dtype,
+                    uint64_t nbytes, uint64_t block_bytes, const ftv_tol *fallback_tol,
+                    uint64_t *fps, uint8_t *blockmap, void *consensus, uint8_t *mask,
+                    ftv_block_stats *bstats, void *stream) {
+  if (!c) return fail(FTV_E_INVALID, "NULL context");
+  if (!replicas || !fallback_tol || !bstats) return fail(FTV_E_INVALID, "NULL argument");
+  if (k < 2 || k > FTV_MAX_K) return fail(FTV_E_K, "k must be in [2, 7]");
+  int rc = check_tol(dtype, *fallback_tol);
+  if (rc) return rc;
+  if (!pow2_in(block_bytes, 4096, 65536))
+    return fail(FTV_E_INVALID, "block_bytes must be a power of two in [4096, 65536]");
+  const uint64_t es = (uint64_t)elem_size(dtype);
+  if (nbytes % es) return fail(FTV_E_INVALID, "nbytes must be a multiple of the element size");
+  if ((uintptr_t)bstats % 8) return fail(FTV_E_ALIGN, "bstats must be 8-byte aligned");
+  const uint64_t nblocks = (nbytes + block_bytes - 1) / block_bytes;
+  if (nblocks > 0x7fffffffull) return fail(FTV_E_INVALID, "too many blocks for one launch");
+  if (nbytes) {
+    if (!blockmap || !consensus) return fail(FTV_E_INVALID, "NULL blockmap or consensus");
+    for (uint32_t r = 0; r < k; ++r) {
+      if (!replicas[r]) return fail(FTV_E_INVALID, "replica pointer is NULL");
+      if ((uintptr_t)replicas[r] % 16) return fail(FTV_E_ALIGN, "replicas must be 16-byte aligned");
+    }
+    if ((uintptr_t)consensus % 16) return fail(FTV_E_ALIGN, "consensus must be 16-byte aligned");
+    if (mask && (uintptr_t)mask % 4) return fail(FTV_E_ALIGN, "mask must be 4-byte aligned");
+    if (fps && (uintptr_t)fps % 8) return fail(FTV_E_ALIGN, "fps must be 8-byte aligned");
+  }
+  BlockVoteD b;
+  memset(&b, 0, sizeof(b));
+  for (uint32_t r = 0; r < k; ++r) b.rep[r] = replicas[r];
+  b.k = k;
+  b.dtype = dtype;
+  b.tolkind = fallback_tol->kind;
+  b.tol = to_tol_d(dtype, *fallback_tol);
+  b.nbytes = nbytes;
+  b.block_bytes = block_bytes;
+  b.nblocks = nblocks;
+  b.fps = fps;
+  b.blockmap = blockmap;
+  b.cons = consensus;
+  b.mask = mask;
+  b.bstats = bstats;
+  b.acc = c->blk_acc;
+  b.ticket = c->blk_ticket;
+  hipError_t e = launch_vote_blocks(b, c->num_cus, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "block vote kernel launch");
+  return FTV_OK;
+}
+
+}  // extern "C"

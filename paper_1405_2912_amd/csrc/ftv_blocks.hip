@@ -1,0 +1,342 @@
+// ftv_blocks.hip -- block fingerprints and the fused block vote for gfx950.
+//
+// Fingerprint of a block (power-of-two size BB in [4 KiB, 64 KiB]): the block
+// is read as little-endian 64-bit words, zero-padded past the end of the
+// buffer; a leaf is 64-bit FNV-1a over 8 consecutive words (64 B) and leaves
+// are combined pairwise, level by level, a node being FNV-1a over the two words
+// (left, right).  One workgroup hashes one block with one leaf per thread:
+// the first six levels of the tree are combined across the lanes of a wave,
+// the remaining ones (up to four, for 16 waves) through LDS.
+//
+// Block vote: the same workgroup hashes the block in all k replicas, votes
+// the k fingerprints by exact equality and writes the block of the
+// lowest-indexed replica holding a strict-majority fingerprint into the
+// consensus -- from registers, where the replicas are held (k <= 5), or by a
+// re-read -- so the restore costs one write pass.  Blocks without a majority
+// fall back to the element vote over their elements.
+#include "ftv_internal.hpp"
+#include "ftv_vote_dev.hpp"
+
+namespace ftv {
+namespace {
+
+using namespace dev;
+
+constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
+
+// (h ^ w) * 0x100000001b3 mod 2^64, with the prime split as 2^40 + 0x1b3.
+__device__ __forceinline__ uint64_t fnv_step(uint64_t h, uint64_t w) {
+  const uint64_t x = h ^ w;
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  const uint64_t p = (uint64_t)lo * 0x1b3u;
+  const uint32_t phi = (uint32_t)(p >> 32) + hi * 0x1b3u + (lo << 8);
+  return ((uint64_t)phi << 32) | (uint32_t)p;
+}
+
+__device__ __forceinline__ uint64_t fnv_node(uint64_t l, uint64_t r) {
+  return fnv_step(fnv_step(kFnvBasis, l), r);
+}
+
+// 64-byte leaf at byte offset `off` of a buffer of `nbytes` (zero beyond).
+__device__ __forceinline__ void load_leaf(const void *base, uint64_t off, uint64_t nbytes,
+                                          u32x4 (&v)[4]) {
+  const uint8_t *b = reinterpret_cast<const uint8_t *>(base);
+  if (off + 64 <= nbytes) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = ld16(b + off, (uint64_t)c);
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint64_t o = off + 16ull * c;
+    if (o + 16 <= nbytes) {
+      v[c] = ld16(b + o, 0);
+    } else {
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
+      for (int q = 0; q < 16; ++q)
+        if (o + q < nbytes) w[q >> 2] |= (uint32_t)b[o + q] << (8 * (q & 3));
+      v[c].x = w[0];
+      v[c].y = w[1];
+      v[c].z = w[2];
+      v[c].w = w[3];
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t leaf_hash(const u32x4 (&v)[4]) {
+  uint64_t h = kFnvBasis;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    h = fnv_step(h, (uint64_t)v[c].x | ((uint64_t)v[c].y << 32));
+    h = fnv_step(h, (uint64_t)v[c].z | ((uint64_t)v[c].w << 32));
+  }
+  return h;
+}
+
+// Combine the leaves of one wave (64 consecutive leaves, one per lane):
+// afterwards lane 0 holds the root of the wave's subtree.
+__device__ __forceinline__ uint64_t wave_tree(uint64_t h) {
+#pragma unroll
+  for (int lvl = 0; lvl < 6; ++lvl) {
+    const uint64_t other = __shfl_xor(h, 1 << lvl, 64);
+    h = fnv_node(h, other);  // meaningful on lanes whose bit `lvl` is clear
+  }
+  return h;
+}
+
+// Reduce `nw` wave roots in LDS (pairwise, in order) to the block root.
+__device__ __forceinline__ uint64_t lds_tree(uint64_t *sh, uint32_t nw) {
+  for (uint32_t len = nw; len > 1; len >>= 1)
+    for (uint32_t j = 0; j < len / 2; ++j) sh[j] = fnv_node(sh[2 * j], sh[2 * j + 1]);
+  return sh[0];
+}
+
+__global__ __launch_bounds__(1024) void k_fingerprint(const void *buf, uint64_t nbytes,
+                                                      uint64_t block_bytes, uint64_t *fp_out) {
+  __shared__ uint64_t sh[16];
+  const uint64_t blk = blockIdx.x;
+  const uint64_t off = blk * block_bytes + (uint64_t)threadIdx.x * 64;
+  u32x4 v[4];
+  load_leaf(buf, off, nbytes, v);
+  const uint64_t h = wave_tree(leaf_hash(v));
+  if ((threadIdx.x & 63u) == 0) sh[threadIdx.x >> 6] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) fp_out[blk] = lds_tree(sh, blockDim.x >> 6);
+}
+
+// ---- block vote ------------------------------------------------------------
+// Workspace accumulators: [0] disagree blocks, [1] fallback blocks,
+// [2] unresolved elements, [3..3+K) replica blocks.
+constexpr int kBlkAcc = 3 + FTV_MAX_K;
+
+// Pass 1: fingerprints of the block in all k replicas, their vote, the block
+// map, and the restore of blocks that have a fingerprint majority.
+template <int K, bool HOLD>
+__global__ __launch_bounds__(1024) void k_vote_blocks(BlockVoteD b) {
+  __shared__ uint64_t sh[K][16];
+  const uint64_t blk = blockIdx.x;
+  const uint64_t off = blk * b.block_bytes + (uint64_t)threadIdx.x * 64;
+  const uint32_t nw = blockDim.x >> 6;
+  constexpr int KH = HOLD ? K : 1;
+  u32x4 x[KH][4];
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    u32x4 v[4];
+    load_leaf(b.rep[r], off, b.nbytes, v);
+    const uint64_t h = wave_tree(leaf_hash(v));
+    if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
+    if constexpr (HOLD) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[r][c] = v[c];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (uint32_t)K) {
+    const uint32_t r = threadIdx.x;
+    const uint64_t f = lds_tree(sh[r], nw);
+    sh[r][0] = f;
+    if (b.fps) b.fps[(uint64_t)r * b.nblocks + blk] = f;
+  }
+  __syncthreads();
+  uint64_t fp_r[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) fp_r[r] = sh[r][0];
+  // vote of the fingerprints (uniform across the workgroup)
+  int M = 0, src = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) s += fp_r[r] == fp_r[j];
+    if (s > M) {
+      M = s;
+      src = r;
+    }
+  }
+  uint32_t bm = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) bm |= (uint32_t)(fp_r[r] != fp_r[src]) << r;
+  const bool majority = 2 * M > K;
+  if (!majority) bm |= 0x80u;
+  uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons);
+  if (majority && off < b.nbytes) {
+    u32x4 v[4];
+    if constexpr (HOLD) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = x[0][c];
+#pragma unroll
+      for (int r = 1; r < K; ++r)
+        if (r == src) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[c] = x[r][c];
+        }
+    } else {
+      load_leaf(b.rep[src], off, b.nbytes, v);
+    }
+    if (off + 64 <= b.nbytes) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) st16(cb + off, (uint64_t)c, v[c], true);
+    } else {
+      const uint32_t *w = reinterpret_cast<const uint32_t *>(v);
+      for (uint64_t q = 0; q < 16 && off + 4 * q < b.nbytes; ++q)
+        reinterpret_cast<uint32_t *>(cb + off)[q] = w[q];
+    }
+    if (b.mask) {
+      const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
+      const uint64_t e0 = off / es;
+      const uint64_t e1 = (off + 64 < b.nbytes ? off + 64 : b.nbytes) / es;
+      if (e1 - e0 == 64 / es) {  // whole piece: 16 (4-byte) or 8 (8-byte) mask bytes
+        uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + e0);
+        for (uint64_t q = 0; q < (64 / es) / 4; ++q) st_nt(mw + q, 0u, true);
+      } else {
+        for (uint64_t e = e0; e < e1; ++e) b.mask[e] = 0;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    b.blockmap[blk] = (uint8_t)bm;
+    if (bm & 0x7fu) atomicAdd((unsigned long long *)&b.acc[0], 1ull);
+    if (!majority) atomicAdd((unsigned long long *)&b.acc[1], 1ull);
+    for (int r = 0; r < K; ++r)
+      if ((bm >> r) & 1u) atomicAdd((unsigned long long *)&b.acc[3 + r], 1ull);
+  }
+}
+
+// Pass 2: element vote of every block without a fingerprint majority (a
+// grid-stride scan of the block map), then the last workgroup writes the
+// stats and clears the workspace.
+template <int DT, int TOL, int K>
+__global__ __launch_bounds__(256) void k_blocks_fallback(BlockVoteD b) {
+  using W = typename VT<DT>::W;
+  __shared__ uint64_t sh[16 * kNumCounters];
+  __shared__ uint32_t s_last;
+  constexpr int NC = Acc<K>::NC;
+  const uint64_t per = b.block_bytes / sizeof(W);
+  const uint64_t n = b.nbytes / sizeof(W);
+  Acc<K> acc;
+  acc.zero();
+  for (uint64_t blk = blockIdx.x; blk < b.nblocks; blk += gridDim.x) {
+    if (!(b.blockmap[blk] & 0x80u)) continue;
+    TaskD t;
+    const uint64_t e0 = blk * per;
+    const uint64_t ne = (e0 + per < n ? e0 + per : n) - e0;
+    for (int r = 0; r < K; ++r) t.rep[r] = reinterpret_cast<const W *>(b.rep[r]) + e0;
+    t.cons = reinterpret_cast<W *>(b.cons) + e0;
+    t.mask = b.mask ? b.mask + e0 : nullptr;
+    t.stats = nullptr;
+    t.n = ne;
+    t.nvec = ne / Vec<W>::V;
+    t.tol = b.tol;
+    t.k = K;
+    vote_range<DT, TOL, K, true, 1>(t, 0, t.nvec, acc, false);
+    vote_tail<DT, TOL, K>(t, acc);
+  }
+  const uint64_t tot = block_total<K>(acc, sh);
+  if (threadIdx.x == (uint32_t)(NC - 1) && tot)
+    atomicAdd((unsigned long long *)&b.acc[2], (unsigned long long)tot);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = __hip_atomic_fetch_add(b.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev + 1 == gridDim.x;
+  }
+  __syncthreads();
+  if (!s_last || threadIdx.x != 0) return;
+  __threadfence();
+  uint64_t a[kBlkAcc];
+  for (int i = 0; i < kBlkAcc; ++i)
+    a[i] = __hip_atomic_load(&b.acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ftv_block_stats *st = b.bstats;
+  st->blocks = b.nblocks;
+  st->disagree_blocks = a[0];
+  st->fallback_blocks = a[1];
+  st->unresolved_elems = a[2];
+  int clean = -1, argmin = 0;
+  for (int r = 0; r < FTV_MAX_K; ++r) {
+    st->replica_blocks[r] = r < K ? a[3 + r] : 0;
+    if (r < K && clean < 0 && a[3 + r] == 0) clean = r;
+    if (r < K && a[3 + r] < a[3 + argmin]) argmin = r;
+  }
+  if (a[0] == 0) {
+    st->verdict = FTV_UNANIMOUS;
+    st->winner = 0;
+  } else if (a[1] == 0 && clean >= 0) {
+    st->verdict = FTV_TASK_MAJORITY;
+    st->winner = clean;
+  } else if (a[2] == 0) {
+    st->verdict = FTV_ELEMENT_MAJORITY;
+    st->winner = argmin;
+  } else {
+    st->verdict = FTV_UNRESOLVED;
+    st->winner = argmin;
+  }
+  for (int i = 0; i < kBlkAcc; ++i)
+    __hip_atomic_store(&b.acc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(b.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_blocks_empty(ftv_block_stats *st) {
+  if (threadIdx.x == 0) {
+    st->blocks = st->disagree_blocks = st->fallback_blocks = st->unresolved_elems = 0;
+    for (int r = 0; r < FTV_MAX_K; ++r) st->replica_blocks[r] = 0;
+    st->verdict = FTV_UNANIMOUS;
+    st->winner = 0;
+  }
+}
+
+template <int DT, int TOL, int K>
+hipError_t launch_fallback(const BlockVoteD &b, int num_cus, hipStream_t s) {
+  uint64_t grid = (uint64_t)num_cus * 4;
+  if (grid > b.nblocks) grid = b.nblocks;
+  hipLaunchKernelGGL((k_blocks_fallback<DT, TOL, K>), dim3((uint32_t)grid), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_blocks_k(const BlockVoteD &b, int num_cus, hipStream_t s) {
+  const dim3 grid((uint32_t)b.nblocks), block((uint32_t)(b.block_bytes / 64));
+  if constexpr (K <= 5) hipLaunchKernelGGL((k_vote_blocks<K, true>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((k_vote_blocks<K, false>), grid, block, 0, s, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (b.dtype * 3 + b.tolkind) {
+    case FTV_F32 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_F32, FTV_TOL_EXACT, K>(b, num_cus, s);
+    case FTV_F32 * 3 + FTV_TOL_ULP: return launch_fallback<FTV_F32, FTV_TOL_ULP, K>(b, num_cus, s);
+    case FTV_F32 * 3 + FTV_TOL_REL: return launch_fallback<FTV_F32, FTV_TOL_REL, K>(b, num_cus, s);
+    case FTV_F64 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_F64, FTV_TOL_EXACT, K>(b, num_cus, s);
+    case FTV_F64 * 3 + FTV_TOL_ULP: return launch_fallback<FTV_F64, FTV_TOL_ULP, K>(b, num_cus, s);
+    case FTV_F64 * 3 + FTV_TOL_REL: return launch_fallback<FTV_F64, FTV_TOL_REL, K>(b, num_cus, s);
+    case FTV_I32 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_I32, FTV_TOL_EXACT, K>(b, num_cus, s);
+    case FTV_I64 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_I64, FTV_TOL_EXACT, K>(b, num_cus, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_bytes,
+                              uint64_t *fp_out, hipStream_t s) {
+  const uint64_t nblocks = (nbytes + block_bytes - 1) / block_bytes;
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fingerprint, dim3((uint32_t)nblocks), dim3((uint32_t)(block_bytes / 64)), 0, s,
+                     buf, nbytes, block_bytes, fp_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vote_blocks(const BlockVoteD &b, int num_cus, hipStream_t s) {
+  if (b.nblocks == 0) {
+    hipLaunchKernelGGL(k_blocks_empty, dim3(1), dim3(64), 0, s, b.bstats);
+    return hipGetLastError();
+  }
+  switch (b.k) {
+    case 2: return launch_blocks_k<2>(b, num_cus, s);
+    case 3: return launch_blocks_k<3>(b, num_cus, s);
+    case 4: return launch_blocks_k<4>(b, num_cus, s);
+    case 5: return launch_blocks_k<5>(b, num_cus, s);
+    case 6: return launch_blocks_k<6>(b, num_cus, s);
+    case 7: return launch_blocks_k<7>(b, num_cus, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ftv

@@ -1,0 +1,100 @@
+// ftv_internal.hpp -- host/device shared declarations of the gfx950 voter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ftv.h"
+
+namespace ftv {
+
+// Tolerance as the kernels see it.  max_ulp is clamped to the key range of the
+// value type on the host so the device compares in the type's own width.
+struct TolD {
+  uint64_t max_ulp;
+  double delta;
+  double abs_floor;
+};
+
+// Specialisation code of a task: value type, tolerance kind and replica count.
+// spec = (dtype * 3 + tolkind) * 8 + k.  Integer types only use EXACT.
+__host__ __device__ constexpr uint32_t spec_code(int dtype, int tolkind, int k) {
+  return (uint32_t)((dtype * 3 + tolkind) * 8 + k);
+}
+
+// A task as the device sees it (per-task launch and batched launch).
+struct TaskD {
+  const void *rep[FTV_MAX_K];
+  void *cons;
+  uint8_t *mask;
+  ftv_stats *stats;
+  uint64_t n;      // elements
+  uint64_t nvec;   // 16-byte vectors (vector path) or elements (scalar path)
+  TolD tol;
+  uint32_t k;
+  uint32_t spec;
+  uint32_t ntiles; // batched launch: tiles of this task
+  uint32_t vec;    // 1 = 16-byte vector path, 0 = scalar path
+};
+
+// One tile of the batched launch: vectors [v0, v1) of task `task`.
+struct TileD {
+  uint32_t task;
+  uint32_t last;   // 1 if this tile also owns the scalar tail of the task
+  uint64_t v0;
+  uint64_t v1;
+};
+
+constexpr int kMaxGrid = 8192;     // per-task launch: workgroups (partials rows)
+constexpr int kNumCounters = 32;   // >= 21 pairs + 7 disagree + 1 no-majority
+
+// Per-workgroup partial counts of the per-task launch, plus its ticket.
+struct VoteWs {
+  uint64_t *partials;  // [kMaxGrid][kNumCounters]
+  uint32_t *ticket;    // self-resetting
+};
+
+int elem_size(int dtype);
+
+// ---- launchers (ftv_vote.hip) -------------------------------------------
+hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
+
+struct BatchLaunch {
+  const TaskD *tasks;     // device
+  const TileD *tiles;     // device
+  const uint64_t *ntiles_dev;  // device: [0] = tiles, [1] = tasks
+  uint64_t *acc;          // device [ntasks][kNumCounters]
+  uint32_t *task_done;    // device [ntasks]
+  uint32_t *queue_head;   // device
+  uint32_t block;
+  uint32_t grid;
+  uint32_t nt_stores;
+};
+hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s);
+
+// ---- fingerprints and block vote (ftv_blocks.hip) ----------------------
+hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_bytes,
+                              uint64_t *fp_out, hipStream_t s);
+
+struct BlockVoteD {
+  const void *rep[FTV_MAX_K];
+  uint32_t k;
+  int32_t dtype;
+  int32_t tolkind;
+  uint32_t pad;
+  TolD tol;
+  uint64_t nbytes;
+  uint64_t block_bytes;
+  uint64_t nblocks;
+  uint64_t *fps;          // may be null
+  uint8_t *blockmap;
+  void *cons;
+  uint8_t *mask;          // may be null
+  ftv_block_stats *bstats;
+  uint64_t *acc;          // device workspace [16]
+  uint32_t *ticket;       // device workspace, self-resetting
+};
+hipError_t launch_vote_blocks(const BlockVoteD &b, int num_cus, hipStream_t s);
+
+}  // namespace ftv

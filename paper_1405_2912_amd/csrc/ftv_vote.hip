@@ -1,0 +1,221 @@
+// ftv_vote.hip -- per-task and batched (persistent) vote kernels for gfx950.
+//
+// Per-task launch: a grid-stride loop over tiles of 16-byte vectors; each
+// workgroup reduces its wave accumulators into one row of partial counts, and
+// the last workgroup to finish (atomic ticket) sums the rows, decides the
+// verdict and writes the whole stats record, then re-arms the ticket.
+//
+// Batched launch: one persistent grid pulls tiles from an atomic queue over a
+// table of (task, vector range) entries; a tile may belong to any task, so the
+// body dispatches on the task's (value type, tolerance, k) code, a
+// workgroup-uniform branch.  Per tile the workgroup adds its non-zero counts
+// to the task's accumulators; the workgroup completing a task's last tile
+// writes the task's stats.
+#include "ftv_internal.hpp"
+#include "ftv_vote_dev.hpp"
+
+namespace ftv {
+namespace {
+
+using namespace dev;
+
+template <int K>
+struct Unroll {
+  static constexpr int value = K <= 3 ? 2 : 1;
+};
+
+template <int DT, int TOL, int K, bool VEC>
+__global__ __launch_bounds__(256) void k_vote_task(TaskD t, VoteWs ws) {
+  __shared__ uint64_t sh[16 * kNumCounters];
+  __shared__ uint64_t s_tot[kNumCounters];
+  __shared__ uint32_t s_last;
+  constexpr int U = Unroll<K>::value;
+  constexpr int NC = Acc<K>::NC;
+  Acc<K> acc;
+  acc.zero();
+  const uint64_t tile = (uint64_t)blockDim.x * U;
+  for (uint64_t b = (uint64_t)blockIdx.x * tile; b < t.nvec; b += (uint64_t)gridDim.x * tile) {
+    const uint64_t e = b + tile < t.nvec ? b + tile : t.nvec;
+    vote_range<DT, TOL, K, VEC, U>(t, b, e, acc, true);
+  }
+  if constexpr (VEC) {
+    if (blockIdx.x == gridDim.x - 1) vote_tail<DT, TOL, K>(t, acc);
+  }
+  const uint64_t tot = block_total<K>(acc, sh);
+  if (threadIdx.x < (uint32_t)kNumCounters)
+    ws.partials[(uint64_t)blockIdx.x * kNumCounters + threadIdx.x] =
+        threadIdx.x < (uint32_t)NC ? tot : 0;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev =
+        __hip_atomic_fetch_add(ws.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // last workgroup: rows are summed by groups of 32 threads, one counter each
+  const uint32_t q = threadIdx.x & 31u, g = threadIdx.x >> 5, ng = blockDim.x >> 5;
+  uint64_t s = 0;
+  for (uint32_t row = g; row < gridDim.x; row += ng)
+    s += __hip_atomic_load(&ws.partials[(uint64_t)row * kNumCounters + q], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  sh[g * kNumCounters + q] = s;
+  __syncthreads();
+  if (threadIdx.x < (uint32_t)kNumCounters) {
+    uint64_t v = 0;
+    for (uint32_t gg = 0; gg < ng; ++gg) v += sh[gg * kNumCounters + threadIdx.x];
+    s_tot[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    write_stats<K>(t.stats, s_tot, t.n);
+    __hip_atomic_store(ws.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---- batched persistent launch -------------------------------------------
+template <int DT, int TOL, int K>
+__device__ __forceinline__ void run_tile(const TaskD &t, const TileD &tile, const BatchLaunch &b,
+                                         uint64_t *sh, uint64_t *s_tot, uint32_t *s_last) {
+  constexpr int U = Unroll<K>::value;
+  constexpr int NC = Acc<K>::NC;
+  Acc<K> acc;
+  acc.zero();
+  vote_range<DT, TOL, K, true, U>(t, tile.v0, tile.v1, acc, b.nt_stores != 0);
+  if (tile.last) vote_tail<DT, TOL, K>(t, acc);
+  const uint64_t tot = block_total<K>(acc, sh);
+  uint64_t *tacc = b.acc + (uint64_t)tile.task * kNumCounters;
+  if (threadIdx.x < (uint32_t)NC && tot != 0)
+    __hip_atomic_fetch_add(&tacc[threadIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = __hip_atomic_fetch_add(&b.task_done[tile.task], 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    *s_last = prev + 1 == t.ntiles;
+  }
+  __syncthreads();
+  if (*s_last) {
+    __threadfence();
+    if (threadIdx.x < (uint32_t)kNumCounters)
+      s_tot[threadIdx.x] =
+          __hip_atomic_load(&tacc[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x == 0) write_stats<K>(t.stats, s_tot, t.n);
+  }
+}
+
+#define FTV_CASE(DT, TOL, K)                                   \
+  case spec_code(DT, TOL, K):                                  \
+    run_tile<DT, TOL, K>(t, tile, b, sh, s_tot, &s_last);      \
+    break;
+#define FTV_CASES_K(DT, TOL) \
+  FTV_CASE(DT, TOL, 2)       \
+  FTV_CASE(DT, TOL, 3)       \
+  FTV_CASE(DT, TOL, 4)       \
+  FTV_CASE(DT, TOL, 5)       \
+  FTV_CASE(DT, TOL, 6)       \
+  FTV_CASE(DT, TOL, 7)
+
+__global__ __launch_bounds__(512) void k_vote_batch(BatchLaunch b) {
+  __shared__ uint64_t sh[16 * kNumCounters];
+  __shared__ uint64_t s_tot[kNumCounters];
+  __shared__ uint32_t s_tile, s_last;
+  const uint64_t ntiles = b.ntiles_dev[0];
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_tile = __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t ti = s_tile;
+    if (ti >= ntiles) break;
+    const TileD tile = b.tiles[ti];
+    const TaskD t = b.tasks[tile.task];
+    switch (t.spec) {
+      FTV_CASES_K(FTV_F32, FTV_TOL_EXACT)
+      FTV_CASES_K(FTV_F32, FTV_TOL_ULP)
+      FTV_CASES_K(FTV_F32, FTV_TOL_REL)
+      FTV_CASES_K(FTV_F64, FTV_TOL_EXACT)
+      FTV_CASES_K(FTV_F64, FTV_TOL_ULP)
+      FTV_CASES_K(FTV_F64, FTV_TOL_REL)
+      FTV_CASES_K(FTV_I32, FTV_TOL_EXACT)
+      FTV_CASES_K(FTV_I64, FTV_TOL_EXACT)
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_zero(BatchLaunch b) {
+  const uint64_t ntasks = b.ntiles_dev[1];
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = gid; i < ntasks * kNumCounters; i += stride) b.acc[i] = 0;
+  for (uint64_t i = gid; i < ntasks; i += stride) b.task_done[i] = 0;
+  if (gid == 0) *b.queue_head = 0;
+}
+
+// ---- per-task dispatch -----------------------------------------------------
+template <int DT, int TOL, int K, bool VEC>
+hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+  constexpr int U = Unroll<K>::value;
+  const uint64_t tile = 256ull * U;
+  uint64_t tiles = (t.nvec + tile - 1) / tile;
+  uint64_t cap = (uint64_t)num_cus * 8;
+  if (cap > (uint64_t)kMaxGrid) cap = kMaxGrid;
+  const uint32_t grid = (uint32_t)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
+  hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(256), 0, s, t, ws);
+  return hipGetLastError();
+}
+
+template <int DT, int TOL, bool VEC>
+hipError_t launch_k(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+  switch (t.k) {
+    case 2: return launch_one<DT, TOL, 2, VEC>(t, ws, num_cus, s);
+    case 3: return launch_one<DT, TOL, 3, VEC>(t, ws, num_cus, s);
+    case 4: return launch_one<DT, TOL, 4, VEC>(t, ws, num_cus, s);
+    case 5: return launch_one<DT, TOL, 5, VEC>(t, ws, num_cus, s);
+    case 6: return launch_one<DT, TOL, 6, VEC>(t, ws, num_cus, s);
+    case 7: return launch_one<DT, TOL, 7, VEC>(t, ws, num_cus, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT, int TOL>
+hipError_t launch_vec(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+  return t.vec ? launch_k<DT, TOL, true>(t, ws, num_cus, s)
+               : launch_k<DT, TOL, false>(t, ws, num_cus, s);
+}
+
+}  // namespace
+
+hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+  const int dtype = (int)(t.spec / 24), tol = (int)((t.spec / 8) % 3);
+  switch (dtype) {
+    case FTV_F32:
+      if (tol == FTV_TOL_EXACT) return launch_vec<FTV_F32, FTV_TOL_EXACT>(t, ws, num_cus, s);
+      if (tol == FTV_TOL_ULP) return launch_vec<FTV_F32, FTV_TOL_ULP>(t, ws, num_cus, s);
+      return launch_vec<FTV_F32, FTV_TOL_REL>(t, ws, num_cus, s);
+    case FTV_F64:
+      if (tol == FTV_TOL_EXACT) return launch_vec<FTV_F64, FTV_TOL_EXACT>(t, ws, num_cus, s);
+      if (tol == FTV_TOL_ULP) return launch_vec<FTV_F64, FTV_TOL_ULP>(t, ws, num_cus, s);
+      return launch_vec<FTV_F64, FTV_TOL_REL>(t, ws, num_cus, s);
+    case FTV_I32: return launch_vec<FTV_I32, FTV_TOL_EXACT>(t, ws, num_cus, s);
+    case FTV_I64: return launch_vec<FTV_I64, FTV_TOL_EXACT>(t, ws, num_cus, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_zero, dim3(64), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_vote_batch, dim3(b.grid), dim3(b.block), 0, s, b);
+  return hipGetLastError();
+}
+
+}  // namespace ftv

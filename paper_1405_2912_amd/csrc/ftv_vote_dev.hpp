@@ -1,0 +1,464 @@
+// ftv_vote_dev.hpp -- device-side element vote for gfx950 (wave64).
+//
+// The voter compares the k results of a duplicated task element by element
+// (Kicherer & Karl, Sec. IV-D): integer values bit-wise, floating-point values
+// within a programmer-set tolerance.  Each element's consensus is chosen among
+// the replicas of maximal support (a strict majority when 2M > k), ties broken
+// by the lower median under IEEE-754 totalOrder of the raw bits, so the result
+// does not depend on the order of the replicas.
+//
+// Layout of the hot loop: every lane streams one 16-byte vector of each of the
+// k replicas per step (global_load_dwordx4, non-temporal), votes the 4 (fp32,
+// i32) or 2 (fp64, i64) elements in registers, and writes one 16-byte
+// consensus vector and 4 or 2 mask bytes.  Mismatch counting is done per wave
+// with ballots into wave-uniform (scalar) accumulators, and only for vectors
+// where some lane saw a disagreement, which is rare.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ftv_internal.hpp"
+
+namespace ftv {
+namespace dev {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int DT>
+struct VT;
+template <>
+struct VT<FTV_F32> {
+  using W = uint32_t;
+  using S = int32_t;
+  static constexpr bool FL = true;
+  static constexpr W SIGN = 0x80000000u;
+  static constexpr W MAG = 0x7fffffffu;
+  static constexpr W INF = 0x7f800000u;
+};
+template <>
+struct VT<FTV_F64> {
+  using W = uint64_t;
+  using S = int64_t;
+  static constexpr bool FL = true;
+  static constexpr W SIGN = 0x8000000000000000ull;
+  static constexpr W MAG = 0x7fffffffffffffffull;
+  static constexpr W INF = 0x7ff0000000000000ull;
+};
+template <>
+struct VT<FTV_I32> {
+  using W = uint32_t;
+  using S = int32_t;
+  static constexpr bool FL = false;
+  static constexpr W SIGN = 0x80000000u;
+  static constexpr W MAG = 0x7fffffffu;
+  static constexpr W INF = 0;
+};
+template <>
+struct VT<FTV_I64> {
+  using W = uint64_t;
+  using S = int64_t;
+  static constexpr bool FL = false;
+  static constexpr W SIGN = 0x8000000000000000ull;
+  static constexpr W MAG = 0x7fffffffffffffffull;
+  static constexpr W INF = 0;
+};
+
+__device__ __forceinline__ double as_double(uint32_t x) { return (double)__uint_as_float(x); }
+__device__ __forceinline__ double as_double(uint64_t x) { return __longlong_as_double((long long)x); }
+
+// Per-replica quantities reused by every pair that replica is part of.
+template <int DT, int TOL>
+struct Pre {
+  using W = typename VT<DT>::W;
+  using S = typename VT<DT>::S;
+  W bits;
+  W mag;
+  S key;       // signed-magnitude bits as two's complement: adjacent floats differ by 1
+  double val;  // REL only
+};
+
+template <int DT, int TOL>
+__device__ __forceinline__ Pre<DT, TOL> prep(typename VT<DT>::W x) {
+  using T = VT<DT>;
+  using S = typename T::S;
+  Pre<DT, TOL> p;
+  p.bits = x;
+  if constexpr (T::FL && TOL != FTV_TOL_EXACT) {
+    p.mag = x & T::MAG;
+    p.key = (x & T::SIGN) ? -(S)p.mag : (S)p.mag;
+    if constexpr (TOL == FTV_TOL_REL) p.val = as_double(x);
+  }
+  return p;
+}
+
+// The voter's equality: bit-wise for integers and EXACT; otherwise NaN equals
+// any NaN, an infinity only the same infinity, and finite values within the
+// tolerance (ULP: key distance; REL: binary64 relative test, no FMA).
+template <int DT, int TOL>
+__device__ __forceinline__ bool eqp(const Pre<DT, TOL> &a, const Pre<DT, TOL> &b, const TolD &t) {
+  using T = VT<DT>;
+  using W = typename T::W;
+  if constexpr (!T::FL || TOL == FTV_TOL_EXACT) {
+    return a.bits == b.bits;
+  } else {
+    if (a.bits == b.bits) return true;
+    const bool an = a.mag > T::INF, bn = b.mag > T::INF;
+    if (an || bn) return an && bn;
+    if (a.mag == T::INF || b.mag == T::INF) return false;
+    if (a.key == b.key) return true;
+    if constexpr (TOL == FTV_TOL_ULP) {
+      const W d = a.key >= b.key ? (W)a.key - (W)b.key : (W)b.key - (W)a.key;
+      return d <= (W)t.max_ulp;
+    } else {
+      const double d = __builtin_fabs(__dsub_rn(a.val, b.val));
+      const double m = __builtin_fmax(__builtin_fabs(a.val), __builtin_fabs(b.val));
+      const double lim = __dmul_rn(t.delta, m);
+      return d <= lim || d <= t.abs_floor;
+    }
+  }
+}
+
+// Unsigned key of IEEE-754 totalOrder (floats) or two's-complement order
+// (integers), and its inverse.
+template <int DT>
+__device__ __forceinline__ typename VT<DT>::W okey(typename VT<DT>::W x) {
+  using T = VT<DT>;
+  if constexpr (T::FL) return (x & T::SIGN) ? ~x : (x | T::SIGN);
+  else return x ^ T::SIGN;
+}
+template <int DT>
+__device__ __forceinline__ typename VT<DT>::W okey_inv(typename VT<DT>::W k) {
+  using T = VT<DT>;
+  if constexpr (T::FL) return (k & T::SIGN) ? (k ^ T::SIGN) : ~k;
+  else return k ^ T::SIGN;
+}
+
+template <typename W>
+__device__ __forceinline__ W umin(W a, W b) { return a < b ? a : b; }
+template <typename W>
+__device__ __forceinline__ W umax(W a, W b) { return a < b ? b : a; }
+
+// Result of voting one element: consensus bits, mask byte, and the set of
+// unequal replica pairs (bit p for pair p in (0,1),(0,2),..,(1,2),.. order).
+template <typename W>
+struct ElemOut {
+  W cons;
+  uint32_t mb;
+  uint32_t ne;
+};
+
+template <int K>
+struct NPair {
+  static constexpr int value = K * (K - 1) / 2;
+};
+
+// Generic k: supports, candidate set, lower median of the candidates by key.
+template <int DT, int TOL, int K>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_elem(const typename VT<DT>::W (&x)[K],
+                                                                 const TolD &t) {
+  using W = typename VT<DT>::W;
+  Pre<DT, TOL> p[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) p[r] = prep<DT, TOL>(x[r]);
+  uint32_t adj[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) adj[r] = 1u << r;
+  uint32_t ne = 0;
+  int q = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+#pragma unroll
+    for (int j = r + 1; j < K; ++j, ++q) {
+      const bool e = eqp<DT, TOL>(p[r], p[j], t);
+      adj[r] |= (uint32_t)e << j;
+      adj[j] |= (uint32_t)e << r;
+      ne |= (uint32_t)(!e) << q;
+    }
+  }
+  ElemOut<W> o;
+  o.ne = ne;
+  if constexpr (K == 2) {
+    // supports are 2,2 (agree) or 1,1 (disagree); either way both replicas
+    // are candidates and the lower median of two is the smaller key.  On a
+    // disagreement the other replica is flagged and there is no majority.
+    const W k0 = okey<DT>(x[0]), k1 = okey<DT>(x[1]);
+    o.cons = okey_inv<DT>(umin(k0, k1));
+    o.mb = ne ? (0x80u | (k0 < k1 ? 2u : 1u)) : 0u;
+  } else if constexpr (K == 3) {
+    const bool e01 = !(ne & 1u), e02 = !(ne & 2u), e12 = !(ne & 4u);
+    const int cnt = (int)e01 + (int)e02 + (int)e12;
+    const W k0 = okey<DT>(x[0]), k1 = okey<DT>(x[1]), k2 = okey<DT>(x[2]);
+    const W med = umax(umin(k0, k1), umin(umax(k0, k1), k2));
+    W kc = med;
+    uint32_t mb = 0;
+    if (cnt == 1) {
+      // one agreeing pair: both members are candidates, take the smaller key
+      kc = e01 ? umin(k0, k1) : (e02 ? umin(k0, k2) : umin(k1, k2));
+      mb = e01 ? 4u : (e02 ? 2u : 1u);
+    } else if (cnt == 2) {
+      // the replica equal to both others is the only one of support 3
+      kc = !e01 ? k2 : (!e02 ? k1 : k0);
+    } else if (cnt == 0) {
+      const uint32_t c = (k0 == med) ? 0u : ((k1 == med) ? 1u : 2u);
+      mb = 0x80u | (7u & ~(1u << c));
+    }
+    o.cons = okey_inv<DT>(kc);
+    o.mb = mb;
+  } else {
+    int s[K];
+    int M = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      s[r] = __popc(adj[r]);
+      M = s[r] > M ? s[r] : M;
+    }
+    uint32_t cm = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) cm |= (uint32_t)(s[r] == M) << r;
+    const int target = (__popc(cm) - 1) >> 1;
+    W ok[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ok[r] = okey<DT>(x[r]);
+    W cv = x[0];
+    uint32_t ac = adj[0];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      int rank = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        rank += (int)(((cm >> j) & 1u) && (ok[j] < ok[r] || (ok[j] == ok[r] && j < r)));
+      if (((cm >> r) & 1u) && rank == target) {
+        cv = x[r];
+        ac = adj[r];
+      }
+    }
+    o.cons = cv;
+    o.mb = (~ac & ((1u << K) - 1u)) | (2 * M > K ? 0u : 0x80u);
+  }
+  return o;
+}
+
+// Wave-uniform mismatch accumulators: pair[NP], disagree[K], no_majority.
+template <int K>
+struct Acc {
+  static constexpr int NP = NPair<K>::value;
+  static constexpr int NC = NP + K + 1;
+  uint64_t c[NC];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) c[i] = 0;
+  }
+  // Count one element per lane; `valid` masks lanes past the end.
+  __device__ __forceinline__ void add(bool valid, uint32_t ne, uint32_t mb) {
+    if (__ballot(valid && ne != 0u) == 0ull) return;  // wave-uniform
+#pragma unroll
+    for (int q = 0; q < NP; ++q) c[q] += __popcll(__ballot(valid && ((ne >> q) & 1u)));
+#pragma unroll
+    for (int r = 0; r < K; ++r) c[NP + r] += __popcll(__ballot(valid && ((mb >> r) & 1u)));
+    c[NP + K] += __popcll(__ballot(valid && (mb & 0x80u)));
+  }
+};
+
+// ---- 16-byte vector <-> words ---------------------------------------------
+template <typename W>
+struct Vec;
+template <>
+struct Vec<uint32_t> {
+  static constexpr int V = 4;
+  __device__ __forceinline__ static void unpack(u32x4 v, uint32_t (&w)[4]) {
+    w[0] = v.x;
+    w[1] = v.y;
+    w[2] = v.z;
+    w[3] = v.w;
+  }
+  __device__ __forceinline__ static u32x4 pack(const uint32_t (&w)[4]) {
+    u32x4 v;
+    v.x = w[0];
+    v.y = w[1];
+    v.z = w[2];
+    v.w = w[3];
+    return v;
+  }
+};
+template <>
+struct Vec<uint64_t> {
+  static constexpr int V = 2;
+  __device__ __forceinline__ static void unpack(u32x4 v, uint64_t (&w)[2]) {
+    w[0] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+    w[1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+  }
+  __device__ __forceinline__ static u32x4 pack(const uint64_t (&w)[2]) {
+    u32x4 v;
+    v.x = (uint32_t)w[0];
+    v.y = (uint32_t)(w[0] >> 32);
+    v.z = (uint32_t)w[1];
+    v.w = (uint32_t)(w[1] >> 32);
+    return v;
+  }
+};
+
+__device__ __forceinline__ u32x4 ld16(const void *base, uint64_t vi) {
+  return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(base) + vi);
+}
+__device__ __forceinline__ void st16(void *base, uint64_t vi, u32x4 v, bool nt) {
+  u32x4 *p = reinterpret_cast<u32x4 *>(base) + vi;
+  if (nt) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(T *p, T v, bool nt) {
+  if (nt) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Vote vectors [v0, v1) of a task with the calling workgroup (vector path:
+// vector = 16 bytes; scalar path: vector = one element).  Lane `tid` handles
+// v0 + tid + u*nthreads for u < U in each step, all loads of a step issued
+// before any vote.
+template <int DT, int TOL, int K, bool VEC, int U>
+__device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t v1, Acc<K> &acc,
+                                           bool nt) {
+  using W = typename VT<DT>::W;
+  constexpr int V = VEC ? Vec<W>::V : 1;
+  const uint32_t nth = blockDim.x;
+  const uint32_t tid = threadIdx.x;
+  const bool wc = t.cons != nullptr, wm = t.mask != nullptr;
+  for (uint64_t base = v0; base < v1; base += (uint64_t)nth * U) {
+    W x[U][K][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t vi = base + (uint64_t)u * nth + tid;
+      const bool valid = vi < v1;
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        if constexpr (VEC) {
+          u32x4 v = {0u, 0u, 0u, 0u};
+          if (valid) v = ld16(t.rep[r], vi);
+          Vec<W>::unpack(v, x[u][r]);
+        } else {
+          x[u][r][0] = valid ? __builtin_nontemporal_load(reinterpret_cast<const W *>(t.rep[r]) + vi)
+                             : (W)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t vi = base + (uint64_t)u * nth + tid;
+      const bool valid = vi < v1;
+      W cv[V];
+      uint32_t mbs = 0;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        W xe[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) xe[r] = x[u][r][e];
+        const ElemOut<W> o = vote_elem<DT, TOL, K>(xe, t.tol);
+        cv[e] = o.cons;
+        mbs |= o.mb << (8 * e);
+        acc.add(valid, o.ne, o.mb);
+      }
+      if (valid) {
+        if constexpr (VEC) {
+          if (wc) st16(t.cons, vi, Vec<W>::pack(cv), nt);
+          if (wm) {
+            if constexpr (V == 4) st_nt(reinterpret_cast<uint32_t *>(t.mask) + vi, mbs, nt);
+            else st_nt(reinterpret_cast<uint16_t *>(t.mask) + vi, (uint16_t)mbs, nt);
+          }
+        } else {
+          if (wc) st_nt(reinterpret_cast<W *>(t.cons) + vi, cv[0], nt);
+          if (wm) t.mask[vi] = (uint8_t)mbs;
+        }
+      }
+    }
+  }
+}
+
+// Elements [nvec*V, n) of a vector-path task (fewer than V), one per lane.
+template <int DT, int TOL, int K>
+__device__ __forceinline__ void vote_tail(const TaskD &t, Acc<K> &acc) {
+  using W = typename VT<DT>::W;
+  constexpr int V = Vec<W>::V;
+  const uint64_t i = t.nvec * V + threadIdx.x;
+  const bool valid = threadIdx.x < V && i < t.n;
+  W xe[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) xe[r] = valid ? reinterpret_cast<const W *>(t.rep[r])[i] : (W)0;
+  const ElemOut<W> o = vote_elem<DT, TOL, K>(xe, t.tol);
+  acc.add(valid, o.ne, o.mb);
+  if (valid) {
+    if (t.cons) reinterpret_cast<W *>(t.cons)[i] = o.cons;
+    if (t.mask) t.mask[i] = (uint8_t)o.mb;
+  }
+}
+
+// Sum the wave accumulators of a workgroup; the result for counter q is
+// returned in thread q (q < NC) of the workgroup.  `sh` holds >= 16*32 u64.
+template <int K>
+__device__ __forceinline__ uint64_t block_total(const Acc<K> &acc, uint64_t *sh) {
+  constexpr int NC = Acc<K>::NC;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t nw = blockDim.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sh[wave * kNumCounters + q] = acc.c[q];
+  }
+  __syncthreads();
+  uint64_t s = 0;
+  if (threadIdx.x < (uint32_t)NC)
+    for (uint32_t w = 0; w < nw; ++w) s += sh[w * kNumCounters + threadIdx.x];
+  __syncthreads();
+  return s;
+}
+
+// Verdict and stats from the task totals tot[q], q < NC (LDS), by one thread.
+__device__ __forceinline__ int pair_index(int K, int r, int j) {  // r < j
+  return r * (2 * K - r - 1) / 2 + (j - r - 1);
+}
+
+template <int K>
+__device__ __forceinline__ void write_stats(ftv_stats *st, const uint64_t *tot, uint64_t n) {
+  constexpr int NP = NPair<K>::value;
+  bool all_zero = true;
+  for (int i = 0; i < NP; ++i) all_zero = all_zero && tot[i] == 0;
+  int best = 0, bestT = -1, argmin = 0;
+  for (int r = 0; r < K; ++r) {
+    int T = 1;  // itself
+    for (int j = 0; j < K; ++j)
+      if (j != r) T += tot[pair_index(K, r < j ? r : j, r < j ? j : r)] == 0;
+    if (T > bestT) {
+      bestT = T;
+      best = r;
+    }
+    if (tot[NP + r] < tot[NP + argmin]) argmin = r;
+  }
+  const uint64_t nomaj = tot[NP + K];
+  int verdict, winner;
+  if (all_zero) {
+    verdict = FTV_UNANIMOUS;
+    winner = 0;
+  } else if (2 * bestT > K) {
+    verdict = FTV_TASK_MAJORITY;
+    winner = best;
+  } else if (nomaj == 0) {
+    verdict = FTV_ELEMENT_MAJORITY;
+    winner = argmin;
+  } else {
+    verdict = FTV_UNRESOLVED;
+    winner = argmin;
+  }
+  for (int r = 0; r < FTV_MAX_K; ++r)
+    for (int j = 0; j < FTV_MAX_K; ++j) {
+      uint64_t v = 0;
+      if (r < K && j < K && r != j) v = tot[pair_index(K, r < j ? r : j, r < j ? j : r)];
+      st->pair[r][j] = v;
+    }
+  for (int r = 0; r < FTV_MAX_K; ++r) st->disagree[r] = r < K ? tot[NP + r] : 0;
+  st->no_majority = nomaj;
+  st->n = n;
+  st->verdict = verdict;
+  st->winner = winner;
+}
+
+}  // namespace dev
+}  // namespace ftv

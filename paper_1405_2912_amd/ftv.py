@@ -1,0 +1,323 @@
+"""ctypes binding of libftv.so -- argument marshalling only.
+
+Every step of the vote, the fingerprints, the block vote, the batched launch
+and the server runs in the gfx950 library; PyTorch only provides device memory
+(tensors) and streams.  If the library is missing, load() raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, c_char_p, c_double, c_int, c_int32, c_int64, c_uint8,
+                    c_uint32, c_uint64, c_void_p)
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libftv.so")
+
+# ---- constants mirrored from include/ftv.h ---------------------------------
+OK, E_INVALID, E_DTYPE, E_K, E_ALIGN, E_HIP, E_NOMEM, E_BUSY, E_NOTREADY, E_CLOSED = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+F32, F64, I32, I64 = 0, 1, 2, 3
+TOL_EXACT, TOL_ULP, TOL_REL = 0, 1, 2
+UNANIMOUS, TASK_MAJORITY, ELEMENT_MAJORITY, UNRESOLVED = 0, 1, 2, 3
+MAX_K = 7
+MASK_NOMAJ = 0x80
+REQ_VOTE, REQ_FINGERPRINT = 0, 1
+
+
+class FtvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ftv error {code}: {msg}")
+        self.code = code
+
+
+class Tol(Structure):
+    _fields_ = [("kind", c_int32), ("reserved", c_uint32), ("max_ulp", c_uint64),
+                ("delta", c_double), ("abs_floor", c_double)]
+
+
+class Stats(Structure):
+    _fields_ = [("pair", c_uint64 * 49), ("disagree", c_uint64 * 7), ("no_majority", c_uint64),
+                ("n", c_uint64), ("verdict", c_int32), ("winner", c_int32)]
+
+
+class VoteDesc(Structure):
+    _fields_ = [("replicas", c_void_p * 7), ("k", c_uint32), ("dtype", c_int32), ("n", c_uint64),
+                ("tol", Tol), ("consensus", c_void_p), ("mask", c_void_p), ("stats", c_void_p)]
+
+
+class BatchCfg(Structure):
+    _fields_ = [("tile_vecs", c_uint32), ("block", c_uint32), ("grid_mult", c_uint32),
+                ("order", c_uint32), ("nt_stores", c_uint32), ("reserved", c_uint32)]
+
+
+class BlockStats(Structure):
+    _fields_ = [("blocks", c_uint64), ("disagree_blocks", c_uint64), ("fallback_blocks", c_uint64),
+                ("unresolved_elems", c_uint64), ("replica_blocks", c_uint64 * 7),
+                ("verdict", c_int32), ("winner", c_int32)]
+
+
+class ServerCfg(Structure):
+    _fields_ = [("hbm_budget_bytes", c_uint64), ("max_slots", c_uint32), ("max_queue", c_uint32),
+                ("chunk_bytes", c_uint64), ("device", c_int32), ("reserved", c_uint32)]
+
+
+class Request(Structure):
+    _fields_ = [("kind", c_int32), ("reserved", c_uint32), ("vote", VoteDesc),
+                ("fp_buf", c_void_p), ("fp_bytes", c_uint64), ("block_bytes", c_uint64),
+                ("t_arrival_ns", c_int64), ("user_tag", c_uint64)]
+
+
+class Result(Structure):
+    _fields_ = [("status", c_int32), ("kind", c_int32), ("stats", Stats), ("consensus", c_void_p),
+                ("mask", c_void_p), ("fps", c_void_p), ("nfps", c_uint64),
+                ("t_arrival_ns", c_int64), ("t_submit_ns", c_int64), ("t_admit_ns", c_int64),
+                ("t_done_ns", c_int64), ("user_tag", c_uint64)]
+
+
+class ServerStats(Structure):
+    _fields_ = [("submitted", c_uint64), ("completed", c_uint64), ("queued", c_uint64),
+                ("in_flight", c_uint64), ("rejected", c_uint64), ("bytes_in_flight", c_uint64),
+                ("peak_bytes_in_flight", c_uint64), ("iterations", c_uint64),
+                ("peak_queue_depth", c_uint64), ("mean_queue_depth", c_double),
+                ("p50_us", c_double), ("p99_us", c_double), ("mean_us", c_double),
+                ("max_us", c_double), ("replica_gbps", c_double)]
+
+
+EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv_ctx_destroy",
+           "ftv_vote", "ftv_vote_batch", "ftv_batch_get_config", "ftv_batch_set_config",
+           "ftv_tune_batch", "ftv_fingerprint", "ftv_vote_blocks", "ftv_server_create",
+           "ftv_submit", "ftv_poll", "ftv_release", "ftv_server_get_stats",
+           "ftv_server_destroy"]
+
+_lib = None
+
+
+def load():
+    """Load libftv.so (built in-tree by build()); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1405_2912_amd.build` (there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    L.ftv_version.restype = c_char_p
+    L.ftv_last_error.restype = c_char_p
+    L.ftv_now_ns.restype = c_int64
+    L.ftv_ctx_create.argtypes = [c_int, POINTER(vp)]
+    L.ftv_ctx_destroy.argtypes = [vp]
+    L.ftv_vote.argtypes = [vp, POINTER(VoteDesc), vp]
+    L.ftv_vote_batch.argtypes = [vp, POINTER(VoteDesc), c_uint64, vp]
+    L.ftv_batch_get_config.argtypes = [vp, POINTER(BatchCfg)]
+    L.ftv_batch_set_config.argtypes = [vp, POINTER(BatchCfg)]
+    L.ftv_tune_batch.argtypes = [vp, POINTER(VoteDesc), c_uint64, vp, c_uint32, POINTER(BatchCfg)]
+    L.ftv_fingerprint.argtypes = [vp, vp, c_uint64, c_uint64, vp, vp]
+    L.ftv_vote_blocks.argtypes = [vp, POINTER(c_void_p), c_uint32, c_int32, c_uint64, c_uint64,
+                                  POINTER(Tol), vp, vp, vp, vp, vp, vp]
+    if hasattr(L, "ftv_server_create"):
+        L.ftv_server_create.argtypes = [POINTER(ServerCfg), POINTER(vp)]
+        L.ftv_submit.argtypes = [vp, POINTER(Request), POINTER(c_uint64)]
+        L.ftv_poll.argtypes = [vp, c_uint64, POINTER(Result), c_int64]
+        L.ftv_release.argtypes = [vp, c_uint64]
+        L.ftv_server_get_stats.argtypes = [vp, POINTER(ServerStats)]
+        L.ftv_server_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        fn = getattr(L, name, None)
+        if fn is not None and name not in ("ftv_version", "ftv_last_error", "ftv_now_ns"):
+            fn.restype = c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise FtvError(rc, load().ftv_last_error().decode())
+
+
+def now_ns() -> int:
+    return int(load().ftv_now_ns())
+
+
+# ---- tolerances ------------------------------------------------------------
+def exact() -> Tol:
+    return Tol(TOL_EXACT, 0, 0, 0.0, 0.0)
+
+
+def ulp(n: int) -> Tol:
+    return Tol(TOL_ULP, 0, int(n), 0.0, 0.0)
+
+
+def rel(delta: float = 1e-3, abs_floor: float = 0.0) -> Tol:
+    return Tol(TOL_REL, 0, 0, float(delta), float(abs_floor))
+
+
+# ---- torch plumbing ----------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t) -> int:
+    torch = _torch()
+    m = {torch.float32: F32, torch.float64: F64, torch.int32: I32, torch.int64: I64}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def stats_tensor(device, count: int = 1):
+    """Device buffer for `count` ftv_stats records (8-byte aligned)."""
+    torch = _torch()
+    return torch.zeros(count * ctypes.sizeof(Stats) // 8, dtype=torch.int64, device=device)
+
+
+def read_stats(buf, index: int = 0) -> dict:
+    raw = buf.detach().cpu().numpy().view(np.uint8)
+    sz = ctypes.sizeof(Stats)
+    s = Stats.from_buffer_copy(raw[index * sz:(index + 1) * sz].tobytes())
+    pair = np.array(s.pair, dtype=np.uint64).reshape(7, 7)
+    return {"pair": pair, "disagree": np.array(s.disagree, dtype=np.uint64),
+            "no_majority": int(s.no_majority), "n": int(s.n), "verdict": int(s.verdict),
+            "winner": int(s.winner)}
+
+
+class Context:
+    """An ftv context on one device (its workspace, batch tables and graph)."""
+
+    def __init__(self, device: int = 0):
+        L = load()
+        h = c_void_p()
+        _check(L.ftv_ctx_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load().ftv_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- batch schedule ---------------------------------------------------------
+    def get_batch_config(self) -> BatchCfg:
+        c = BatchCfg()
+        _check(load().ftv_batch_get_config(self.handle, ctypes.byref(c)))
+        return c
+
+    def set_batch_config(self, cfg: BatchCfg):
+        _check(load().ftv_batch_set_config(self.handle, ctypes.byref(cfg)))
+
+
+def make_desc(replicas, tol: Tol, consensus=None, mask=None, stats=None, n=None) -> VoteDesc:
+    d = VoteDesc()
+    k = len(replicas)
+    for r, t in enumerate(replicas):
+        d.replicas[r] = t.data_ptr()
+    d.k = k
+    d.dtype = dtype_code(replicas[0])
+    d.n = int(replicas[0].numel() if n is None else n)
+    d.tol = tol
+    d.consensus = consensus.data_ptr() if consensus is not None else None
+    d.mask = mask.data_ptr() if mask is not None else None
+    d.stats = stats.data_ptr() if stats is not None else None
+    return d
+
+
+def vote(ctx: Context, replicas, tol: Tol, consensus=None, mask=None, stats=None, stream=None,
+         want_consensus: bool = True, want_mask: bool = True):
+    """ftv_vote on k device tensors of one dtype; returns (consensus, mask, stats buffer)."""
+    torch = _torch()
+    x0 = replicas[0]
+    if consensus is None and want_consensus:
+        consensus = torch.empty_like(x0)
+    if mask is None and want_mask:
+        mask = torch.empty(x0.numel(), dtype=torch.uint8, device=x0.device)
+    if stats is None:
+        stats = stats_tensor(x0.device)
+    d = make_desc(replicas, tol, consensus, mask, stats)
+    _check(load().ftv_vote(ctx.handle, ctypes.byref(d), c_void_p(_stream_handle(stream))))
+    return consensus, mask, stats
+
+
+def vote_batch(ctx: Context, descs, stream=None):
+    arr = (VoteDesc * len(descs))(*descs)
+    _check(load().ftv_vote_batch(ctx.handle, arr, len(descs), c_void_p(_stream_handle(stream))))
+
+
+def tune_batch(ctx: Context, descs, iters: int = 3, stream=None) -> BatchCfg:
+    arr = (VoteDesc * len(descs))(*descs)
+    best = BatchCfg()
+    _check(load().ftv_tune_batch(ctx.handle, arr, len(descs), c_void_p(_stream_handle(stream)),
+                                 int(iters), ctypes.byref(best)))
+    return best
+
+
+def fingerprint(ctx: Context, buf, block_bytes: int = 65536, out=None, stream=None):
+    torch = _torch()
+    nbytes = buf.numel() * buf.element_size()
+    nblocks = (nbytes + block_bytes - 1) // block_bytes
+    if out is None:
+        out = torch.empty(nblocks, dtype=torch.int64, device=buf.device)
+    _check(load().ftv_fingerprint(ctx.handle, c_void_p(buf.data_ptr()), nbytes, block_bytes,
+                                  c_void_p(out.data_ptr()), c_void_p(_stream_handle(stream))))
+    return out
+
+
+def block_stats_tensor(device):
+    torch = _torch()
+    return torch.zeros(ctypes.sizeof(BlockStats) // 8, dtype=torch.int64, device=device)
+
+
+def read_block_stats(buf) -> dict:
+    raw = buf.detach().cpu().numpy().view(np.uint8).tobytes()
+    s = BlockStats.from_buffer_copy(raw[:ctypes.sizeof(BlockStats)])
+    return {"blocks": int(s.blocks), "disagree_blocks": int(s.disagree_blocks),
+            "fallback_blocks": int(s.fallback_blocks), "unresolved_elems": int(s.unresolved_elems),
+            "replica_blocks": np.array(s.replica_blocks, dtype=np.uint64),
+            "verdict": int(s.verdict), "winner": int(s.winner)}
+
+
+def vote_blocks(ctx: Context, replicas, fallback_tol: Tol, block_bytes: int = 65536,
+                want_fps: bool = True, want_mask: bool = True, consensus=None, mask=None,
+                blockmap=None, fps=None, bstats=None, stream=None):
+    """ftv_vote_blocks; returns dict of device tensors (fps, blockmap, consensus, mask, bstats)."""
+    torch = _torch()
+    x0 = replicas[0]
+    k = len(replicas)
+    nbytes = x0.numel() * x0.element_size()
+    nblocks = (nbytes + block_bytes - 1) // block_bytes
+    dev = x0.device
+    if fps is None and want_fps:
+        fps = torch.empty(k * nblocks, dtype=torch.int64, device=dev)
+    if blockmap is None:
+        blockmap = torch.empty(max(nblocks, 1), dtype=torch.uint8, device=dev)
+    if consensus is None:
+        consensus = torch.empty_like(x0)
+    if mask is None and want_mask:
+        mask = torch.empty(x0.numel(), dtype=torch.uint8, device=dev)
+    if bstats is None:
+        bstats = block_stats_tensor(dev)
+    ptrs = (c_void_p * k)(*[t.data_ptr() for t in replicas])
+    tol = fallback_tol
+    _check(load().ftv_vote_blocks(
+        ctx.handle, ptrs, k, dtype_code(x0), nbytes, block_bytes, ctypes.byref(tol),
+        c_void_p(fps.data_ptr()) if fps is not None else None, c_void_p(blockmap.data_ptr()),
+        c_void_p(consensus.data_ptr()), c_void_p(mask.data_ptr()) if mask is not None else None,
+        c_void_p(bstats.data_ptr()), c_void_p(_stream_handle(stream))))
+    return {"fps": fps, "blockmap": blockmap[:nblocks], "consensus": consensus, "mask": mask,
+            "bstats": bstats}

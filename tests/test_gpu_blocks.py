@@ -1,0 +1,150 @@
+"""GPU parity of block fingerprints and the fused block vote with consensus
+restore, against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = gpu.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("bb", [4096, 8192, 65536])
+def test_fingerprint_parity(gpu, ctx, bb):
+    import torch
+    rng = np.random.default_rng(bb)
+    for nbytes in (1, 7, 8, 63, 64, 100, 4095, 4096, 4097, 65536, 3 * 65536 + 13, (1 << 20) + 24):
+        raw = rng.integers(0, 256, nbytes, dtype=np.uint8)
+        t = torch.from_numpy(raw).cuda()
+        print(f"case: fingerprint nbytes={nbytes} block={bb}", flush=True)
+        fp = gpu.fingerprint(ctx, t, bb)
+        torch.cuda.synchronize()
+        got = fp.cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, oracle.fingerprint(raw, bb)), nbytes
+
+
+def _block_case(gpu, reps, tol_o, tol_f, bb, want_fps=True, want_mask=True):
+    import torch
+    t = [torch.from_numpy(r).cuda() for r in reps]
+    out = gpu.vote_blocks(ctx_holder[0], t, tol_f, bb, want_fps=want_fps, want_mask=want_mask)
+    torch.cuda.synchronize()
+    ref = oracle.vote_blocks(reps, tol_o, bb)
+    k = len(reps)
+    u = np.uint32 if reps[0].itemsize == 4 else np.uint64
+    if want_fps:
+        assert np.array_equal(out["fps"].cpu().numpy().view(np.uint64).reshape(k, -1), ref.fps)
+    assert np.array_equal(out["blockmap"].cpu().numpy(), ref.blockmap)
+    assert np.array_equal(out["consensus"].cpu().numpy().view(u), ref.consensus.view(u))
+    if want_mask:
+        assert np.array_equal(out["mask"].cpu().numpy(), ref.mask)
+    s = gpu.read_block_stats(out["bstats"])
+    assert (s["blocks"], s["disagree_blocks"], s["fallback_blocks"], s["unresolved_elems"]) == \
+        (ref.blocks, ref.disagree_blocks, ref.fallback_blocks, ref.unresolved_elems)
+    assert np.array_equal(s["replica_blocks"][:k], ref.replica_blocks)
+    assert (s["verdict"], s["winner"]) == (ref.verdict, ref.winner)
+    return ref
+
+
+ctx_holder = []
+
+
+@pytest.fixture(autouse=True)
+def _hold(ctx):
+    ctx_holder[:] = [ctx]
+    yield
+
+
+def test_config5_recipe_reduced(gpu):
+    n = 1 << 19   # 4 MiB per replica, 64 blocks of 64 KiB
+    reps = synth.config5(n, nstuck=40, nflip=20)
+    base = reps[0]
+    # forced: a stuck word (r1) and a flip (r2) in the same block -> no majority
+    b = 17 * 8192
+    reps[1][b + 5] = 0.0
+    reps[2].view(np.uint64)[b + 900] ^= np.uint64(1 << 51)
+    print("case: config-5 recipe, 2^19 fp64, k=5", flush=True)
+    ref = _block_case(gpu, reps, oracle.exact(), gpu.exact(), 65536)
+    assert ref.fallback_blocks >= 1 and np.array_equal(ref.consensus.view(np.uint64), base.view(np.uint64))
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7])
+def test_block_vote_k_dtype_matrix(gpu, k):
+    rng = np.random.default_rng(k)
+    for dtype, tol_o, tol_f, bb in ((np.float64, oracle.ulp(2), gpu.ulp(2), 4096),
+                                     (np.float32, oracle.rel(1e-3), gpu.rel(1e-3), 16384),
+                                     (np.int32, oracle.exact(), gpu.exact(), 8192)):
+        n = (3 * bb + 520) // np.dtype(dtype).itemsize   # ragged last block
+        base = synth.values("f64" if dtype == np.float64 else ("f32" if dtype == np.float32 else "i32"),
+                            synth.INTFULL if dtype == np.int32 else synth.NORMAL, 3, 0, n)
+        reps = [base.copy() for _ in range(k)]
+        per = bb // np.dtype(dtype).itemsize
+        for r in range(1, k):
+            for blk in rng.choice(4, size=2, replace=False):
+                i = min(n - 1, int(blk) * per + int(rng.integers(0, per)))
+                reps[r].view(np.uint32 if dtype != np.float64 else np.uint64)[i] ^= 1 << int(rng.integers(0, 20))
+        print(f"case: block vote k={k} {np.dtype(dtype).name} block={bb}", flush=True)
+        _block_case(gpu, reps, tol_o, tol_f, bb)
+        _block_case(gpu, reps, tol_o, tol_f, bb, want_fps=False, want_mask=False)
+
+
+def test_block_vote_empty_and_tiny(gpu):
+    for n in (0, 1, 5):
+        reps = [np.arange(n, dtype=np.float64) for _ in range(3)]
+        if n:
+            reps[1][0] = 9.0
+        print(f"case: block vote n={n}", flush=True)
+        _block_case(gpu, reps, oracle.exact(), gpu.exact(), 4096)
+
+
+def test_config5_full_size(gpu):
+    """k=5 fp64 16384x16384 checkpoint: every fault-carrying block plus a random
+    sample of blocks checked against the oracle, and the block-level counts
+    against the fault plan."""
+    import torch
+    import synth.device as sd
+    n = 16384 * 16384
+    bb = 65536
+    per = bb // 8
+    print("case: config-5 full size", flush=True)
+    reps = sd.config5(n)
+    fb = 4321
+    reps[1][fb * per + 3] = 0.0                       # forced no-majority block
+    iv = reps[2].view(torch.int64)
+    iv[fb * per + 777] ^= (1 << 33)
+    out = gpu.vote_blocks(ctx_holder[0], reps, gpu.exact(), bb)
+    torch.cuda.synchronize()
+    s = gpu.read_block_stats(out["bstats"])
+    nblocks = n // per
+    diff = [(reps[r].view(torch.int64) != reps[0].view(torch.int64)).view(nblocks, per).any(dim=1).cpu().numpy()
+            for r in range(5)]
+    assert s["blocks"] == nblocks
+    assert s["replica_blocks"][0] == 0 and s["replica_blocks"][4] == 0
+    assert s["replica_blocks"][1] == diff[1].sum() and s["replica_blocks"][2] == diff[2].sum()
+    assert s["replica_blocks"][3] == diff[3].sum() == nblocks
+    nofall = diff[1] & diff[2]
+    assert s["fallback_blocks"] == nofall.sum() >= 1
+    assert s["unresolved_elems"] == 0 and s["verdict"] == gpu.ELEMENT_MAJORITY
+    assert s["disagree_blocks"] == nblocks
+    cons = out["consensus"]
+    assert torch.equal(cons.view(torch.int64), reps[0].view(torch.int64))
+    blockmap = out["blockmap"].cpu().numpy()
+    fps = out["fps"].cpu().numpy().view(np.uint64).reshape(5, nblocks)
+    mask = out["mask"]
+    rng = np.random.default_rng(5)
+    sample = sorted(set(np.nonzero(diff[1] | diff[2])[0].tolist()) |
+                    set(rng.choice(nblocks, 40, replace=False).tolist()) | {0, nblocks - 1, fb})
+    for blk in sample:
+        sl = slice(blk * per, (blk + 1) * per)
+        rb = [r[sl].cpu().numpy() for r in reps]
+        ref = oracle.vote_blocks(rb, oracle.exact(), bb)
+        assert np.array_equal(fps[:, blk], ref.fps[:, 0]), blk
+        assert blockmap[blk] == ref.blockmap[0], blk
+        assert np.array_equal(cons[sl].cpu().numpy().view(np.uint64), ref.consensus.view(np.uint64)), blk
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), blk
