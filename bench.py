@@ -100,6 +100,244 @@ def main_vote(ftv, ctx, steps, warmup, side):
             "alg_bytes": alg_bytes, "stats": s, "n": n}
 
 
+# ---------------------------------------------------------------------------
+# batched uneven tasks: one persistent launch vs one launch per task
+# ---------------------------------------------------------------------------
+def make_uneven_tasks(ftv, ntasks: int, seed: int, max_bytes: int = 64 << 20):
+    import numpy as np
+    import torch
+    import synth
+    import synth.device as sd
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(np.log(1024), np.log(max_bytes), ntasks)) / 8).astype(np.int64) * 8
+    dts = rng.choice(["f32", "f64", "i32"], size=ntasks, p=[0.5, 0.3, 0.2])
+    ks = rng.choice([2, 3, 5], size=ntasks, p=[0.2, 0.6, 0.2])
+    faulty = set(rng.choice(ntasks, max(1, round(0.01 * ntasks)), replace=False).tolist())
+    es = {"f32": 4, "f64": 8, "i32": 4}
+    al = lambda b: (int(b) + 255) // 256 * 256
+    rep_bytes = sum(al(sizes[i]) * int(ks[i]) for i in range(ntasks))
+    out_bytes = sum(al(sizes[i]) for i in range(ntasks))
+    mask_bytes = sum(al(sizes[i] // es[dts[i]]) for i in range(ntasks))
+    dev = torch.device("cuda:0")
+    rep_arena = torch.empty(rep_bytes, dtype=torch.uint8, device=dev)
+    tdt = {"f32": torch.float32, "f64": torch.float64, "i32": torch.int32}
+    tasks = []
+    ro = 0
+    for i in range(ntasks):
+        dt, k, b = str(dts[i]), int(ks[i]), int(sizes[i])
+        n = b // es[dt]
+        reps = []
+        for r in range(k):
+            t = rep_arena[ro:ro + b].view(tdt[dt])
+            ro += al(b)
+            sd.fill(t, dt, synth.INTFULL if dt == "i32" else synth.UNIFORM, seed, i * 8)
+            reps.append(t)
+        if dt != "i32":
+            sd.ulp_noise(reps[1], dt, seed, i * 8 + 1, round(0.10 * (1 << 24)), 1)
+        if i in faulty and n:
+            victim = int(rng.integers(0, k))
+            nflip = int(rng.integers(1, 65))
+            pos, bits = synth.flip_plan(n, min(nflip, n), 8 * es[dt], seed + i, 7)
+            sd.flip_bits(reps[victim], pos, bits)
+        tol = ftv.exact() if dt == "i32" else (ftv.ulp(4) if dt == "f32" else ftv.ulp(2))
+        tasks.append(dict(reps=reps, n=n, k=k, dt=dt, tol=tol))
+    sizes_info = dict(rep_bytes=sum(int(sizes[i]) * int(ks[i]) for i in range(ntasks)),
+                      cons_bytes=int(sizes.sum()),
+                      mask_bytes=int(sum(int(sizes[i]) // es[dts[i]] for i in range(ntasks))))
+    return tasks, sizes_info, (out_bytes, mask_bytes)
+
+
+def output_set(ftv, tasks, out_sizes):
+    import ctypes
+    import torch
+    dev = torch.device("cuda:0")
+    out_bytes, mask_bytes = out_sizes
+    cons = torch.empty(out_bytes, dtype=torch.uint8, device=dev)
+    mask = torch.empty(mask_bytes, dtype=torch.uint8, device=dev)
+    stats = ftv.stats_tensor(dev, len(tasks))
+    descs = []
+    co = mo = 0
+    for i, t in enumerate(tasks):
+        es = 8 if t["dt"] == "f64" else 4
+        d = ftv.make_desc(t["reps"], t["tol"], None, None, None, n=t["n"])
+        d.consensus = cons.data_ptr() + co
+        d.mask = mask.data_ptr() + mo
+        d.stats = stats.data_ptr() + i * ctypes.sizeof(ftv.Stats)
+        co += (t["n"] * es + 255) // 256 * 256
+        mo += (t["n"] + 255) // 256 * 256
+        descs.append(d)
+    return cons, mask, stats, descs
+
+
+def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10):
+    import ctypes
+    import numpy as np
+    import torch
+    import oracle
+    log(f"bench: generating {ntasks} uneven tasks on the device")
+    tasks, info, out_sizes = make_uneven_tasks(ftv, ntasks, 14052912 + 3)
+    cons_b, mask_b, st_b, descs_b = output_set(ftv, tasks, out_sizes)
+    cons_p, mask_p, st_p, descs_p = output_set(ftv, tasks, out_sizes)
+    torch.cuda.synchronize()
+    log("bench: autotuning the batched schedule")
+    best = ftv.tune_batch(ctx, descs_b, iters=2)
+    torch.cuda.synchronize()
+    log("bench: timing batched launches")
+    ftv.vote_batch(ctx, descs_b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps_timed):
+        ftv.vote_batch(ctx, descs_b)
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - t0) / reps_timed * 1e3
+    log("bench: timing per-task launches")
+    L = ftv.load()
+    h = ctx.handle
+    stream = ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+    arr = [ctypes.byref(d) for d in descs_p]
+    for a in arr:
+        L.ftv_vote(h, a, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pt_rounds = 3
+    for _ in range(pt_rounds):
+        for a in arr:
+            L.ftv_vote(h, a, stream)
+    torch.cuda.synchronize()
+    per_task_ms = (time.perf_counter() - t0) / pt_rounds * 1e3
+    equal = bool(torch.equal(cons_b, cons_p) and torch.equal(mask_b, mask_p) and torch.equal(st_b, st_p))
+    # oracle on a sample of tasks (smallest ones + a few random)
+    order = np.argsort([t["n"] for t in tasks])
+    sample = list(order[:12]) + list(np.random.default_rng(1).choice(len(tasks), 4, replace=False))
+    ok = 0
+    for i in sample:
+        t = tasks[int(i)]
+        if t["n"] > (1 << 22):
+            continue
+        host = [r.cpu().numpy() for r in t["reps"]]
+        otol = oracle.exact() if t["dt"] == "i32" else oracle.ulp(t["tol"].max_ulp)
+        ref = oracle.vote(host, otol)
+        s = ftv.read_stats(st_b, int(i))
+        d = descs_b[int(i)]
+        es = host[0].itemsize
+        c = cons_b[(d.consensus - cons_b.data_ptr()):(d.consensus - cons_b.data_ptr()) + t["n"] * es].cpu().numpy()
+        m = mask_b[(d.mask - mask_b.data_ptr()):(d.mask - mask_b.data_ptr()) + t["n"]].cpu().numpy()
+        good = (np.array_equal(c, ref.consensus.view(np.uint8)) and np.array_equal(m, ref.mask)
+                and s["verdict"] == ref.verdict and s["no_majority"] == ref.no_majority)
+        ok += int(good)
+    alg = info["rep_bytes"] + info["cons_bytes"] + info["mask_bytes"]
+    res = {"workload": f"{ntasks} tasks, bytes per replica log-uniform [1 KiB, 64 MiB], fp32/fp64/i32 "
+                       f"50/30/20%, k in {{2,3,5}} 20/60/20%, 1% faulty tasks",
+           "replica_bytes": info["rep_bytes"], "alg_bytes": alg,
+           "batched_ms": round(batched_ms, 3), "per_task_ms": round(per_task_ms, 3),
+           "speedup": round(per_task_ms / batched_ms, 3),
+           "batched_replica_gbps": round(info["rep_bytes"] / batched_ms / 1e6, 1),
+           "batched_hbm_frac": round(alg / batched_ms / 1e6 / HBM_PEAK_GBS, 4),
+           "per_task_replica_gbps": round(info["rep_bytes"] / per_task_ms / 1e6, 1),
+           "identical_results": equal, "oracle_sampled_ok": f"{ok}/{len(sample)}",
+           "tuned": {"tile_vecs": best.tile_vecs, "block": best.block, "grid_mult": best.grid_mult,
+                     "order": best.order, "nt_stores": best.nt_stores}}
+    del tasks, cons_b, mask_b, cons_p, mask_p
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---------------------------------------------------------------------------
+# checkpoint validation plus vote (k = 5 fp64, 64 KiB blocks)
+# ---------------------------------------------------------------------------
+def bench_blocks(ftv, ctx, side=16384, reps_timed=10):
+    import torch
+    import synth.device as sd
+    n = side * side
+    log(f"bench: generating the k=5 fp64 {side}x{side} checkpoint replicas")
+    reps = sd.config5(n)
+    per = 8192
+    fb = 4321 % (n // per)
+    reps[1][fb * per + 3] = 0.0
+    reps[2].view(torch.int64)[fb * per + 777] ^= (1 << 33)
+    out = ftv.vote_blocks(ctx, reps, ftv.exact(), 65536)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps_timed):
+        ftv.vote_blocks(ctx, reps, ftv.exact(), 65536, fps=out["fps"], blockmap=out["blockmap"],
+                        consensus=out["consensus"], mask=out["mask"], bstats=out["bstats"])
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps_timed
+    s = ftv.read_block_stats(out["bstats"])
+    nblocks = n // per
+    alg = 5 * n * 8 + n * 8 + n + 5 * nblocks * 8 + nblocks
+    restored = bool(torch.equal(out["consensus"].view(torch.int64), reps[0].view(torch.int64)))
+    res = {"workload": f"k=5 fp64 {side}x{side} checkpoint, 64 KiB blocks, stuck words, flips, a shifted "
+                       f"replica, one forced no-majority block",
+           "ms": round(ms, 4), "replica_gbps": round(5 * n * 8 / ms / 1e6, 1),
+           "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+           "blocks": s["blocks"], "disagree_blocks": s["disagree_blocks"],
+           "fallback_blocks": s["fallback_blocks"], "unresolved_elems": s["unresolved_elems"],
+           "verdict": s["verdict"], "consensus_equals_clean_replica": restored}
+    del reps, out
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---------------------------------------------------------------------------
+# serving: Poisson arrivals, continuous batching, p50/p99 latency
+# ---------------------------------------------------------------------------
+def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0):
+    import numpy as np
+    import torch
+    import synth.device as sd
+    pool_elems = (256 << 20) // 4
+    log("bench: serving pool (3 x 256 MiB fp32 replicas with the large-task faults)")
+    pool = sd.config2(pool_elems, "f32", flip_rate=1e-7 * 64)
+    srv = ftv.Server(hbm_budget_bytes=64 << 30, arena_bytes=24 << 30, chunk_bytes=32 << 20,
+                     max_slots=1024, max_queue=1 << 20)
+    rng = np.random.default_rng(14052912 + 4)
+    count = int(seconds * rate)
+    gaps = rng.exponential(1.0 / rate, count)
+    sizes = np.floor(np.exp(rng.uniform(np.log(4096), np.log(256 << 20), count)) / 4).astype(np.int64)
+    offs = [int(rng.integers(0, (pool_elems - int(n)) // 64 + 1)) * 64 for n in sizes]
+    tol = ftv.ulp(4)
+    log(f"bench: serving {count} requests at {rate:.0f}/s")
+    t0 = ftv.now_ns() + 5_000_000
+    arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
+    outstanding = []
+    max_out = 0
+    for i in range(count):
+        ta = int(arrivals[i])
+        while True:
+            now = ftv.now_ns()
+            if now >= ta:
+                break
+            # release finished requests while waiting for the next arrival
+            while outstanding and srv.poll(outstanding[0], 0) is not None:
+                srv.release(outstanding.pop(0))
+            if ta - ftv.now_ns() > 200_000:
+                time.sleep(0.0001)
+        n, o = int(sizes[i]), offs[i]
+        reps = [p[o:o + n] for p in pool]
+        outstanding.append(srv.submit_vote(reps, tol, t_arrival_ns=ta, n=n))
+        max_out = max(max_out, len(outstanding))
+        if len(outstanding) > 64 and srv.poll(outstanding[0], 0) is not None:
+            srv.release(outstanding.pop(0))
+    for tk in outstanding:
+        srv.poll(tk, -1)
+        srv.release(tk)
+    st = srv.stats()
+    srv.close()
+    del pool
+    torch.cuda.empty_cache()
+    return {"workload": f"Poisson {rate:.0f} req/s for {seconds:g} s, sizes log-uniform [4 KiB, 256 MiB] per "
+                        f"replica, k=3 fp32, budget 64 GiB",
+            "requests": int(st["completed"]), "p50_us": round(st["p50_us"], 1),
+            "p99_us": round(st["p99_us"], 1), "mean_us": round(st["mean_us"], 1),
+            "max_us": round(st["max_us"], 1), "mean_queue_depth": round(st["mean_queue_depth"], 3),
+            "peak_queue_depth": int(st["peak_queue_depth"]), "iterations": int(st["iterations"]),
+            "served_replica_gbps": round(st["replica_gbps"], 2),
+            "peak_bytes_in_flight": int(st["peak_bytes_in_flight"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +346,8 @@ def main():
     ap.add_argument("--side", type=int, default=16384)
     ap.add_argument("--main-only", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=27)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--batch-tasks", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the voter's multi-GPU "
@@ -151,6 +391,10 @@ def main():
     out["cpu_baseline"] = cpu_baseline(m["reps"], 1 << args.cpu_sample_log2)
     del m
     torch.cuda.empty_cache()
+    if not args.main_only:
+        out["batched"] = bench_batched(ftv, ctx, args.batch_tasks)
+        out["blocks"] = bench_blocks(ftv, ctx)
+        out["serving"] = bench_serving(ftv, ctx, args.serve_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -232,13 +232,16 @@ int ftv_vote_blocks(ftv_ctx *ctx, const void *const *replicas, uint32_t k, int32
 typedef struct ftv_server ftv_server;
 
 typedef struct ftv_server_cfg {
-  uint64_t hbm_budget_bytes; /* admitted footprint limit (inputs + outputs) */
-  uint32_t max_slots;        /* requests admitted at once, <= 4096 */
+  uint64_t hbm_budget_bytes; /* admitted footprint limit: replica inputs held
+                                while in flight + outputs until released */
+  uint64_t arena_bytes;      /* device memory the server carves outputs from for
+                                requests that pass NULL outputs (0 = none) */
+  uint64_t chunk_bytes;      /* per-request bytes per replica per iteration */
+  uint32_t max_slots;        /* requests admitted at once, 1..4096 */
   uint32_t max_queue;        /* queued (not yet admitted) requests; submit
                                 returns FTV_E_BUSY beyond it */
-  uint64_t chunk_bytes;      /* per-request bytes per replica per iteration */
   int32_t device;
-  uint32_t reserved;
+  uint32_t reserved;         /* must be 0 */
 } ftv_server_cfg;
 
 #define FTV_REQ_VOTE 0

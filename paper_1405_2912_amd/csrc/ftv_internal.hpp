@@ -72,6 +72,9 @@ struct BatchLaunch {
 };
 hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s);
+// Serving: zero queue_head and the accumulators of slots[0..hdr[2]).
+hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, uint32_t *done,
+                             const uint32_t *slots, const uint64_t *hdr, hipStream_t s);
 
 // ---- fingerprints and block vote (ftv_blocks.hip) ----------------------
 hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_bytes,

@@ -157,13 +157,45 @@ __global__ __launch_bounds__(256) void k_batch_zero(BatchLaunch b) {
   if (gid == 0) *b.queue_head = 0;
 }
 
+// Serving iterations: re-arm the tile queue and clear the accumulators of the
+// slots whose requests join in this iteration (slots[0..hdr[2]) ).
+__global__ __launch_bounds__(256) void k_slots_init(uint32_t *queue_head, uint64_t *acc,
+                                                    uint32_t *done, const uint32_t *slots,
+                                                    const uint64_t *hdr) {
+  const uint64_t nnew = hdr[2];
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = gid; i < nnew * kNumCounters; i += stride)
+    acc[(uint64_t)slots[i / kNumCounters] * kNumCounters + i % kNumCounters] = 0;
+  for (uint64_t i = gid; i < nnew; i += stride) done[slots[i]] = 0;
+  if (gid == 0) *queue_head = 0;
+}
+
 // ---- per-task dispatch -----------------------------------------------------
+// Workgroups of this instance that fit on one CU at once.  The grid-stride
+// loop is only balanced when every workgroup of the grid is resident: a grid
+// larger than the machine leaves a second, mostly empty wave of workgroups.
+template <int DT, int TOL, int K, bool VEC>
+int resident_per_cu() {
+  static const int nb = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_vote_task<DT, TOL, K, VEC>, 256, 0) !=
+            hipSuccess ||
+        v < 1) {
+      (void)hipGetLastError();
+      v = 4;
+    }
+    return v;
+  }();
+  return nb;
+}
+
 template <int DT, int TOL, int K, bool VEC>
 hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
   constexpr int U = Unroll<K>::value;
   const uint64_t tile = 256ull * U;
   uint64_t tiles = (t.nvec + tile - 1) / tile;
-  uint64_t cap = (uint64_t)num_cus * 8;
+  uint64_t cap = (uint64_t)num_cus * resident_per_cu<DT, TOL, K, VEC>();
   if (cap > (uint64_t)kMaxGrid) cap = kMaxGrid;
   const uint32_t grid = (uint32_t)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
   hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(256), 0, s, t, ws);
@@ -210,6 +242,12 @@ hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipSt
 
 hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_zero, dim3(64), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, uint32_t *done,
+                             const uint32_t *slots, const uint64_t *hdr, hipStream_t s) {
+  hipLaunchKernelGGL(k_slots_init, dim3(32), dim3(256), 0, s, queue_head, acc, done, slots, hdr);
   return hipGetLastError();
 }
 

@@ -64,6 +64,11 @@ struct VT<FTV_I64> {
   static constexpr W INF = 0;
 };
 
+template <typename W>
+__device__ __forceinline__ W umin(W a, W b) { return a < b ? a : b; }
+template <typename W>
+__device__ __forceinline__ W umax(W a, W b) { return a < b ? b : a; }
+
 __device__ __forceinline__ double as_double(uint32_t x) { return (double)__uint_as_float(x); }
 __device__ __forceinline__ double as_double(uint64_t x) { return __longlong_as_double((long long)x); }
 
@@ -94,7 +99,8 @@ __device__ __forceinline__ Pre<DT, TOL> prep(typename VT<DT>::W x) {
 
 // The voter's equality: bit-wise for integers and EXACT; otherwise NaN equals
 // any NaN, an infinity only the same infinity, and finite values within the
-// tolerance (ULP: key distance; REL: binary64 relative test, no FMA).
+// tolerance (ULP: key distance; REL: binary64 relative test, no FMA).  Written
+// without early exits so that it compiles to selects, not branches.
 template <int DT, int TOL>
 __device__ __forceinline__ bool eqp(const Pre<DT, TOL> &a, const Pre<DT, TOL> &b, const TolD &t) {
   using T = VT<DT>;
@@ -102,21 +108,27 @@ __device__ __forceinline__ bool eqp(const Pre<DT, TOL> &a, const Pre<DT, TOL> &b
   if constexpr (!T::FL || TOL == FTV_TOL_EXACT) {
     return a.bits == b.bits;
   } else {
-    if (a.bits == b.bits) return true;
     const bool an = a.mag > T::INF, bn = b.mag > T::INF;
-    if (an || bn) return an && bn;
-    if (a.mag == T::INF || b.mag == T::INF) return false;
-    if (a.key == b.key) return true;
+    const bool fin = (a.mag < T::INF) & (b.mag < T::INF);
+    bool within;
     if constexpr (TOL == FTV_TOL_ULP) {
-      const W d = a.key >= b.key ? (W)a.key - (W)b.key : (W)b.key - (W)a.key;
-      return d <= (W)t.max_ulp;
+      // keys biased by 2^(w-1) into unsigned range: the distance is |ua - ub|
+      const W ua = (a.bits & T::SIGN) ? (W)(T::SIGN - a.mag) : (a.mag | T::SIGN);
+      const W ub = (b.bits & T::SIGN) ? (W)(T::SIGN - b.mag) : (b.mag | T::SIGN);
+      within = (umax(ua, ub) - umin(ua, ub)) <= (W)t.max_ulp;
     } else {
       const double d = __builtin_fabs(__dsub_rn(a.val, b.val));
       const double m = __builtin_fmax(__builtin_fabs(a.val), __builtin_fabs(b.val));
       const double lim = __dmul_rn(t.delta, m);
-      return d <= lim || d <= t.abs_floor;
+      within = ((a.mag | b.mag) == 0) | (d <= lim) | (d <= t.abs_floor);
     }
+    return (a.bits == b.bits) | (an & bn) | (fin & within);
   }
+}
+
+template <int DT, int TOL>
+__device__ __forceinline__ bool eqv(typename VT<DT>::W a, typename VT<DT>::W b, const TolD &t) {
+  return eqp<DT, TOL>(prep<DT, TOL>(a), prep<DT, TOL>(b), t);
 }
 
 // Unsigned key of IEEE-754 totalOrder (floats) or two's-complement order
@@ -134,10 +146,6 @@ __device__ __forceinline__ typename VT<DT>::W okey_inv(typename VT<DT>::W k) {
   else return k ^ T::SIGN;
 }
 
-template <typename W>
-__device__ __forceinline__ W umin(W a, W b) { return a < b ? a : b; }
-template <typename W>
-__device__ __forceinline__ W umax(W a, W b) { return a < b ? b : a; }
 
 // Result of voting one element: consensus bits, mask byte, and the set of
 // unequal replica pairs (bit p for pair p in (0,1),(0,2),..,(1,2),.. order).
@@ -153,10 +161,61 @@ struct NPair {
   static constexpr int value = K * (K - 1) / 2;
 };
 
+// k = 3 when the three bit patterns may all differ: the case analysis on the
+// number of agreeing pairs (3 or 0: median; 2: the replica agreeing with both;
+// 1: the smaller key of the agreeing pair).
+template <int DT>
+__device__ __forceinline__ typename VT<DT>::W vote3_general(const typename VT<DT>::W (&x)[3],
+                                                            uint32_t ne, uint32_t &mb_out) {
+  using W = typename VT<DT>::W;
+  const bool e01 = !(ne & 1u), e02 = !(ne & 2u), e12 = !(ne & 4u);
+  const int cnt = (int)e01 + (int)e02 + (int)e12;
+  const W k0 = okey<DT>(x[0]), k1 = okey<DT>(x[1]), k2 = okey<DT>(x[2]);
+  const W med = umax(umin(k0, k1), umin(umax(k0, k1), k2));
+  const W pairmin = e01 ? umin(k0, k1) : (e02 ? umin(k0, k2) : umin(k1, k2));
+  const W vertex = !e01 ? k2 : (!e02 ? k1 : k0);
+  const W kc = cnt == 1 ? pairmin : (cnt == 2 ? vertex : med);
+  const uint32_t cmed = (k0 == med) ? 0u : ((k1 == med) ? 1u : 2u);
+  const uint32_t odd = e01 ? 4u : (e02 ? 2u : 1u);
+  mb_out = cnt == 1 ? odd : (cnt == 0 ? (0x80u | (7u & ~(1u << cmed))) : 0u);
+  return okey_inv<DT>(kc);
+}
+
+// k = 3.  If two replicas are bit-identical their value is the consensus in
+// every case (with the third equal to it all three are candidates and the
+// pair holds the median; otherwise the pair are the only candidates), so one
+// tolerance test -- third against the pair -- decides the element.  Only
+// elements whose three bit patterns all differ take the general path.
+template <int DT, int TOL>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote3(const typename VT<DT>::W (&x)[3],
+                                                             const TolD &t) {
+  using W = typename VT<DT>::W;
+  ElemOut<W> o;
+  const bool i01 = x[0] == x[1], i02 = x[0] == x[2], i12 = x[1] == x[2];
+  const W pv = (i01 | i02) ? x[0] : x[1];
+  const W xt = i01 ? x[2] : (i02 ? x[1] : x[0]);
+  const uint32_t third = i01 ? 2u : (i02 ? 1u : 0u);
+  const bool e = eqv<DT, TOL>(xt, pv, t);
+  // pairs (0,1)=bit0 (0,2)=bit1 (1,2)=bit2 that involve the third replica
+  const uint32_t tpairs = third == 2u ? 6u : (third == 1u ? 5u : 3u);
+  o.cons = pv;
+  o.mb = e ? 0u : (1u << third);
+  o.ne = e ? 0u : tpairs;
+  if (!(i01 | i02 | i12)) {
+    const Pre<DT, TOL> p0 = prep<DT, TOL>(x[0]), p1 = prep<DT, TOL>(x[1]), p2 = prep<DT, TOL>(x[2]);
+    const uint32_t ne = (uint32_t)!eqp<DT, TOL>(p0, p1, t) | ((uint32_t)!eqp<DT, TOL>(p0, p2, t) << 1) |
+                        ((uint32_t)!eqp<DT, TOL>(p1, p2, t) << 2);
+    o.ne = ne;
+    o.cons = vote3_general<DT>(x, ne, o.mb);
+  }
+  return o;
+}
+
 // Generic k: supports, candidate set, lower median of the candidates by key.
 template <int DT, int TOL, int K>
-__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_elem(const typename VT<DT>::W (&x)[K],
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general(const typename VT<DT>::W (&x)[K],
                                                                  const TolD &t) {
+
   using W = typename VT<DT>::W;
   Pre<DT, TOL> p[K];
 #pragma unroll
@@ -186,25 +245,7 @@ __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_elem(const typename 
     o.cons = okey_inv<DT>(umin(k0, k1));
     o.mb = ne ? (0x80u | (k0 < k1 ? 2u : 1u)) : 0u;
   } else if constexpr (K == 3) {
-    const bool e01 = !(ne & 1u), e02 = !(ne & 2u), e12 = !(ne & 4u);
-    const int cnt = (int)e01 + (int)e02 + (int)e12;
-    const W k0 = okey<DT>(x[0]), k1 = okey<DT>(x[1]), k2 = okey<DT>(x[2]);
-    const W med = umax(umin(k0, k1), umin(umax(k0, k1), k2));
-    W kc = med;
-    uint32_t mb = 0;
-    if (cnt == 1) {
-      // one agreeing pair: both members are candidates, take the smaller key
-      kc = e01 ? umin(k0, k1) : (e02 ? umin(k0, k2) : umin(k1, k2));
-      mb = e01 ? 4u : (e02 ? 2u : 1u);
-    } else if (cnt == 2) {
-      // the replica equal to both others is the only one of support 3
-      kc = !e01 ? k2 : (!e02 ? k1 : k0);
-    } else if (cnt == 0) {
-      const uint32_t c = (k0 == med) ? 0u : ((k1 == med) ? 1u : 2u);
-      mb = 0x80u | (7u & ~(1u << c));
-    }
-    o.cons = okey_inv<DT>(kc);
-    o.mb = mb;
+    o.cons = vote3_general<DT>(x, ne, o.mb);
   } else {
     int s[K];
     int M = 0;
@@ -237,6 +278,29 @@ __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_elem(const typename 
     o.mb = (~ac & ((1u << K) - 1u)) | (2 * M > K ? 0u : 0x80u);
   }
   return o;
+}
+
+// Vote of one element.  k = 2 and k = 3 have closed forms; larger k skip the
+// general computation when all k bit patterns are identical.
+template <int DT, int TOL, int K>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_elem(const typename VT<DT>::W (&x)[K],
+                                                                 const TolD &t) {
+  using W = typename VT<DT>::W;
+  if constexpr (K == 3) {
+    return vote3<DT, TOL>(x, t);
+  } else if constexpr (K == 2) {
+    return vote_general<DT, TOL, 2>(x, t);
+  } else {
+    bool same = true;
+#pragma unroll
+    for (int r = 1; r < K; ++r) same = same & (x[r] == x[0]);
+    ElemOut<W> o;
+    o.cons = x[0];
+    o.mb = 0;
+    o.ne = 0;
+    if (!same) o = vote_general<DT, TOL, K>(x, t);
+    return o;
+  }
 }
 
 // Wave-uniform mismatch accumulators: pair[NP], disagree[K], no_majority.
@@ -326,19 +390,32 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
   const bool wc = t.cons != nullptr, wm = t.mask != nullptr;
   for (uint64_t base = v0; base < v1; base += (uint64_t)nth * U) {
     W x[U][K][V];
+    const bool full = base + (uint64_t)U * nth <= v1;  // workgroup-uniform
+    if (full) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t vi = base + (uint64_t)u * nth + tid;
-      const bool valid = vi < v1;
+      for (int u = 0; u < U; ++u) {
+        const uint64_t vi = base + (uint64_t)u * nth + tid;
 #pragma unroll
-      for (int r = 0; r < K; ++r) {
-        if constexpr (VEC) {
-          u32x4 v = {0u, 0u, 0u, 0u};
-          if (valid) v = ld16(t.rep[r], vi);
-          Vec<W>::unpack(v, x[u][r]);
-        } else {
-          x[u][r][0] = valid ? __builtin_nontemporal_load(reinterpret_cast<const W *>(t.rep[r]) + vi)
-                             : (W)0;
+        for (int r = 0; r < K; ++r) {
+          if constexpr (VEC) Vec<W>::unpack(ld16(t.rep[r], vi), x[u][r]);
+          else x[u][r][0] = __builtin_nontemporal_load(reinterpret_cast<const W *>(t.rep[r]) + vi);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t vi = base + (uint64_t)u * nth + tid;
+        const bool valid = vi < v1;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+          if constexpr (VEC) {
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (valid) v = ld16(t.rep[r], vi);
+            Vec<W>::unpack(v, x[u][r]);
+          } else {
+            x[u][r][0] = valid ? __builtin_nontemporal_load(reinterpret_cast<const W *>(t.rep[r]) + vi)
+                               : (W)0;
+          }
         }
       }
     }

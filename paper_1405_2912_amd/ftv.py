@@ -61,8 +61,9 @@ class BlockStats(Structure):
 
 
 class ServerCfg(Structure):
-    _fields_ = [("hbm_budget_bytes", c_uint64), ("max_slots", c_uint32), ("max_queue", c_uint32),
-                ("chunk_bytes", c_uint64), ("device", c_int32), ("reserved", c_uint32)]
+    _fields_ = [("hbm_budget_bytes", c_uint64), ("arena_bytes", c_uint64), ("chunk_bytes", c_uint64),
+                ("max_slots", c_uint32), ("max_queue", c_uint32), ("device", c_int32),
+                ("reserved", c_uint32)]
 
 
 class Request(Structure):
@@ -321,3 +322,77 @@ def vote_blocks(ctx: Context, replicas, fallback_tol: Tol, block_bytes: int = 65
         c_void_p(bstats.data_ptr()), c_void_p(_stream_handle(stream))))
     return {"fps": fps, "blockmap": blockmap[:nblocks], "consensus": consensus, "mask": mask,
             "bstats": bstats}
+
+
+# ---- serving ---------------------------------------------------------------
+class Server:
+    """Continuous-batching voter service (ftv_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, arena_bytes: int = 0, chunk_bytes: int = 32 << 20,
+                 max_slots: int = 1024, max_queue: int = 1 << 20, device: int = 0):
+        L = load()
+        cfg = ServerCfg(int(hbm_budget_bytes), int(arena_bytes), int(chunk_bytes), int(max_slots),
+                        int(max_queue), int(device), 0)
+        h = c_void_p()
+        _check(L.ftv_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, req: Request) -> int:
+        t = c_uint64()
+        _check(load().ftv_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        return int(t.value)
+
+    def submit_vote(self, replicas, tol: Tol, consensus=None, mask=None, t_arrival_ns: int = 0,
+                    user_tag: int = 0, n=None) -> int:
+        req = Request()
+        req.kind = REQ_VOTE
+        req.vote = make_desc(replicas, tol, consensus, mask, None, n=n)
+        req.t_arrival_ns = int(t_arrival_ns)
+        req.user_tag = int(user_tag)
+        return self.submit(req)
+
+    def submit_fingerprint(self, buf, block_bytes: int = 65536, t_arrival_ns: int = 0,
+                           user_tag: int = 0) -> int:
+        req = Request()
+        req.kind = REQ_FINGERPRINT
+        req.fp_buf = buf.data_ptr()
+        req.fp_bytes = buf.numel() * buf.element_size()
+        req.block_bytes = int(block_bytes)
+        req.t_arrival_ns = int(t_arrival_ns)
+        req.user_tag = int(user_tag)
+        return self.submit(req)
+
+    def poll(self, ticket: int, wait_us: int = -1):
+        """Result structure when done, None while in flight."""
+        res = Result()
+        rc = load().ftv_poll(self.handle, int(ticket), ctypes.byref(res), int(wait_us))
+        if rc == E_NOTREADY:
+            return None
+        _check(rc)
+        return res
+
+    def release(self, ticket: int):
+        _check(load().ftv_release(self.handle, int(ticket)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().ftv_server_get_stats(self.handle, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            load().ftv_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def result_stats(res: Result) -> dict:
+    s = res.stats
+    return {"pair": np.array(s.pair, dtype=np.uint64).reshape(7, 7),
+            "disagree": np.array(s.disagree, dtype=np.uint64), "no_majority": int(s.no_majority),
+            "n": int(s.n), "verdict": int(s.verdict), "winner": int(s.winner)}
