@@ -334,6 +334,8 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0):
             "p99_us": round(st["p99_us"], 1), "mean_us": round(st["mean_us"], 1),
             "max_us": round(st["max_us"], 1), "mean_queue_depth": round(st["mean_queue_depth"], 3),
             "peak_queue_depth": int(st["peak_queue_depth"]), "iterations": int(st["iterations"]),
+            "shared_iterations": int(st["shared_iterations"]),
+            "max_requests_per_iteration": int(st["max_requests_per_iteration"]),
             "served_replica_gbps": round(st["replica_gbps"], 2),
             "peak_bytes_in_flight": int(st["peak_bytes_in_flight"])}
 
@@ -348,6 +350,8 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=27)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--batch-tasks", type=int, default=4096)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run two plain 1 GiB device copies (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the voter's multi-GPU "
@@ -358,6 +362,13 @@ def main():
     import paper_1405_2912_amd as ftv
     ftv.load()
     ctx = ftv.Context(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(7)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     m = main_vote(ftv, ctx, args.steps, args.warmup, args.side)
     ms_per_step = m["wall"] / args.steps * 1e3
     value = m["replica_bytes"] / (ms_per_step / 1e3) / 1e9

@@ -277,6 +277,8 @@ typedef struct ftv_server_stats {
   uint64_t submitted, completed, queued, in_flight, rejected;
   uint64_t bytes_in_flight, peak_bytes_in_flight;
   uint64_t iterations, peak_queue_depth;
+  uint64_t shared_iterations;          /* iterations that carried work of 2+ requests */
+  uint64_t max_requests_per_iteration;
   double mean_queue_depth;   /* time-averaged queued requests */
   double p50_us, p99_us;     /* arrival -> completion, completed requests */
   double mean_us, max_us;

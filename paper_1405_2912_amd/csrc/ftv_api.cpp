@@ -104,7 +104,7 @@ struct ftv_ctx {
   int device = 0;
   int num_cus = 256;
   std::string name;
-  // per-task launch workspace
+  // per-task launch workspace: count accumulators (zero between launches)
   uint64_t *partials = nullptr;
   uint32_t *ticket = nullptr;
   // batched launch
@@ -395,7 +395,8 @@ int ftv_ctx_create(int device, ftv_ctx **out) {
   c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->name = prop.gcnArchName;
   c->cfg = kDefaultCfg;
-  bool ok = hipMalloc(&c->partials, sizeof(uint64_t) * kMaxGrid * kNumCounters) == hipSuccess &&
+  bool ok = hipMalloc(&c->partials, sizeof(uint64_t) * kNumCounters) == hipSuccess &&
+            hipMemset(c->partials, 0, sizeof(uint64_t) * kNumCounters) == hipSuccess &&
             hipMalloc(&c->ticket, 256) == hipSuccess && hipMalloc(&c->d_queue, 256) == hipSuccess &&
             hipMalloc(&c->blk_acc, 256) == hipSuccess && hipMalloc(&c->blk_ticket, 256) == hipSuccess &&
             hipMemset(c->ticket, 0, 256) == hipSuccess && hipMemset(c->blk_ticket, 0, 256) == hipSuccess &&

@@ -9,11 +9,12 @@
 // the remaining ones (up to four, for 16 waves) through LDS.
 //
 // Block vote: the same workgroup hashes the block in all k replicas, votes
-// the k fingerprints by exact equality and writes the block of the
-// lowest-indexed replica holding a strict-majority fingerprint into the
-// consensus -- from registers, where the replicas are held (k <= 5), or by a
-// re-read -- so the restore costs one write pass.  Blocks without a majority
-// fall back to the element vote over their elements.
+// the k fingerprints by exact equality and restores the consensus from the
+// lowest-indexed replica holding a strict-majority fingerprint.  Replica 0's
+// data is streamed into the consensus while it is hashed, so in the common
+// case (replica 0 agrees with the majority) the restore costs one write pass
+// and no extra read.  Blocks without a majority fall back to the element vote
+// over their elements in a second, small kernel.
 #include "ftv_internal.hpp"
 #include "ftv_vote_dev.hpp"
 
@@ -52,13 +53,21 @@ __device__ __forceinline__ void load_leaf(const void *base, uint64_t off, uint64
     if (o + 16 <= nbytes) {
       v[c] = ld16(b + o, 0);
     } else {
-      uint32_t w[4] = {0u, 0u, 0u, 0u};
-      for (int q = 0; q < 16; ++q)
-        if (o + q < nbytes) w[q >> 2] |= (uint32_t)b[o + q] << (8 * (q & 3));
-      v[c].x = w[0];
-      v[c].y = w[1];
-      v[c].z = w[2];
-      v[c].w = w[3];
+      // partial chunk at the end of the buffer: bytes one by one, zero beyond
+      uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const uint32_t byte = (o + q < nbytes) ? (uint32_t)b[o + q] : 0u;
+        const uint32_t sh = byte << (8 * (q & 3));
+        if (q < 4) w0 |= sh;
+        else if (q < 8) w1 |= sh;
+        else if (q < 12) w2 |= sh;
+        else w3 |= sh;
+      }
+      v[c].x = w0;
+      v[c].y = w1;
+      v[c].z = w2;
+      v[c].w = w3;
     }
   }
 }
@@ -109,25 +118,91 @@ __global__ __launch_bounds__(1024) void k_fingerprint(const void *buf, uint64_t 
 // [2] unresolved elements, [3..3+K) replica blocks.
 constexpr int kBlkAcc = 3 + FTV_MAX_K;
 
+// Store a 64-byte piece at byte offset `off` of the consensus (bytes past the
+// end are not written) and zero the mask bytes of its elements.
+__device__ __forceinline__ void put_piece(const BlockVoteD &b, uint64_t off, const u32x4 (&v)[4],
+                                          bool mask_too) {
+  uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons);
+  if (off + 64 <= b.nbytes) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) st16(cb + off, (uint64_t)c, v[c], true);
+  } else {
+    // the buffer ends inside this piece (its size is a multiple of 4 bytes)
+    uint32_t *dst = reinterpret_cast<uint32_t *>(cb + off);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (off + 16ull * c + 0 < b.nbytes) dst[4 * c + 0] = v[c].x;
+      if (off + 16ull * c + 4 < b.nbytes) dst[4 * c + 1] = v[c].y;
+      if (off + 16ull * c + 8 < b.nbytes) dst[4 * c + 2] = v[c].z;
+      if (off + 16ull * c + 12 < b.nbytes) dst[4 * c + 3] = v[c].w;
+    }
+  }
+  if (mask_too && b.mask) {
+    const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
+    const uint64_t e0 = off / es;
+    const uint64_t e1 = (off + 64 < b.nbytes ? off + 64 : b.nbytes) / es;
+    if (e1 - e0 == 64 / es) {  // whole piece: 16 (4-byte) or 8 (8-byte) mask bytes
+      uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + e0);
+      for (uint64_t q = 0; q < (64 / es) / 4; ++q) st_nt(mw + q, 0u, true);
+    } else {
+      for (uint64_t e = e0; e < e1; ++e) b.mask[e] = 0;
+    }
+  }
+}
+
+// b.rep[r] for a runtime r, as a select chain: indexing the by-value kernel
+// argument with a runtime index would copy it to scratch memory.
+template <int K>
+__device__ __forceinline__ const void *rep_ptr(const BlockVoteD &b, int r) {
+  const void *p = b.rep[0];
+#pragma unroll
+  for (int j = 1; j < K; ++j) p = (j == r) ? b.rep[j] : p;
+  return p;
+}
+
 // Pass 1: fingerprints of the block in all k replicas, their vote, the block
-// map, and the restore of blocks that have a fingerprint majority.
-template <int K, bool HOLD>
-__global__ __launch_bounds__(1024) void k_vote_blocks(BlockVoteD b) {
+// map, and the restore.  Replica 0's piece is written to the consensus while
+// it is hashed (one leaf per lane is live at a time); only a block whose
+// majority fingerprint differs from replica 0's is copied again, from the
+// source replica.  Blocks without a majority are left to pass 2, which
+// rewrites their consensus and mask.
+template <int K>
+__global__ __launch_bounds__(1024, 8) void k_vote_blocks(BlockVoteD b) {
   __shared__ uint64_t sh[K][16];
   const uint64_t blk = blockIdx.x;
   const uint64_t off = blk * b.block_bytes + (uint64_t)threadIdx.x * 64;
   const uint32_t nw = blockDim.x >> 6;
-  constexpr int KH = HOLD ? K : 1;
-  u32x4 x[KH][4];
+  // one replica at a time (not unrolled): a single leaf per lane is live, which
+  // keeps two 1024-lane workgroups resident per CU to overlap their phases.
+  // Whole blocks (all but possibly the last) take a path without bounds tests.
+  if ((blk + 1) * b.block_bytes <= b.nbytes) {
+    const uint8_t *cb = reinterpret_cast<const uint8_t *>(b.cons);
+#pragma unroll 1
+    for (int r = 0; r < K; ++r) {
+      const uint8_t *p = reinterpret_cast<const uint8_t *>(rep_ptr<K>(b, r)) + off;
+      u32x4 v[4];
 #pragma unroll
-  for (int r = 0; r < K; ++r) {
-    u32x4 v[4];
-    load_leaf(b.rep[r], off, b.nbytes, v);
-    const uint64_t h = wave_tree(leaf_hash(v));
-    if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
-    if constexpr (HOLD) {
+      for (int c = 0; c < 4; ++c) v[c] = ld16(p, (uint64_t)c);
+      if (r == 0) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) x[r][c] = v[c];
+        for (int c = 0; c < 4; ++c) st16((void *)(cb + off), (uint64_t)c, v[c], true);
+        if (b.mask) {
+          const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
+          uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + off / es);
+          for (uint64_t q = 0; q < (64 / es) / 4; ++q) st_nt(mw + q, 0u, true);
+        }
+      }
+      const uint64_t h = wave_tree(leaf_hash(v));
+      if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
+    }
+  } else {
+#pragma unroll 1
+    for (int r = 0; r < K; ++r) {
+      u32x4 v[4];
+      load_leaf(rep_ptr<K>(b, r), off, b.nbytes, v);
+      if (r == 0 && off < b.nbytes) put_piece(b, off, v, true);
+      const uint64_t h = wave_tree(leaf_hash(v));
+      if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
     }
   }
   __syncthreads();
@@ -158,40 +233,10 @@ __global__ __launch_bounds__(1024) void k_vote_blocks(BlockVoteD b) {
   for (int r = 0; r < K; ++r) bm |= (uint32_t)(fp_r[r] != fp_r[src]) << r;
   const bool majority = 2 * M > K;
   if (!majority) bm |= 0x80u;
-  uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons);
-  if (majority && off < b.nbytes) {
+  if (majority && (bm & 1u) && off < b.nbytes) {  // replica 0 is not the majority: recopy
     u32x4 v[4];
-    if constexpr (HOLD) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = x[0][c];
-#pragma unroll
-      for (int r = 1; r < K; ++r)
-        if (r == src) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) v[c] = x[r][c];
-        }
-    } else {
-      load_leaf(b.rep[src], off, b.nbytes, v);
-    }
-    if (off + 64 <= b.nbytes) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) st16(cb + off, (uint64_t)c, v[c], true);
-    } else {
-      const uint32_t *w = reinterpret_cast<const uint32_t *>(v);
-      for (uint64_t q = 0; q < 16 && off + 4 * q < b.nbytes; ++q)
-        reinterpret_cast<uint32_t *>(cb + off)[q] = w[q];
-    }
-    if (b.mask) {
-      const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
-      const uint64_t e0 = off / es;
-      const uint64_t e1 = (off + 64 < b.nbytes ? off + 64 : b.nbytes) / es;
-      if (e1 - e0 == 64 / es) {  // whole piece: 16 (4-byte) or 8 (8-byte) mask bytes
-        uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + e0);
-        for (uint64_t q = 0; q < (64 / es) / 4; ++q) st_nt(mw + q, 0u, true);
-      } else {
-        for (uint64_t e = e0; e < e1; ++e) b.mask[e] = 0;
-      }
-    }
+    load_leaf(rep_ptr<K>(b, src), off, b.nbytes, v);
+    put_piece(b, off, v, false);
   }
   if (threadIdx.x == 0) {
     b.blockmap[blk] = (uint8_t)bm;
@@ -215,19 +260,26 @@ __global__ __launch_bounds__(256) void k_blocks_fallback(BlockVoteD b) {
   const uint64_t n = b.nbytes / sizeof(W);
   Acc<K> acc;
   acc.zero();
+  // the block's task record lives in LDS: a local record indexed at run time
+  // (the rare general vote does) would be placed in scratch memory
+  __shared__ TaskD t;
   for (uint64_t blk = blockIdx.x; blk < b.nblocks; blk += gridDim.x) {
     if (!(b.blockmap[blk] & 0x80u)) continue;
-    TaskD t;
     const uint64_t e0 = blk * per;
     const uint64_t ne = (e0 + per < n ? e0 + per : n) - e0;
-    for (int r = 0; r < K; ++r) t.rep[r] = reinterpret_cast<const W *>(b.rep[r]) + e0;
-    t.cons = reinterpret_cast<W *>(b.cons) + e0;
-    t.mask = b.mask ? b.mask + e0 : nullptr;
-    t.stats = nullptr;
-    t.n = ne;
-    t.nvec = ne / Vec<W>::V;
-    t.tol = b.tol;
-    t.k = K;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int r = 0; r < FTV_MAX_K; ++r)
+        t.rep[r] = r < K ? (const void *)(reinterpret_cast<const W *>(b.rep[r]) + e0) : nullptr;
+      t.cons = reinterpret_cast<W *>(b.cons) + e0;
+      t.mask = b.mask ? b.mask + e0 : nullptr;
+      t.stats = nullptr;
+      t.n = ne;
+      t.nvec = ne / Vec<W>::V;
+      t.tol = b.tol;
+      t.k = K;
+    }
+    __syncthreads();
     vote_range<DT, TOL, K, true, 1>(t, 0, t.nvec, acc, false);
     vote_tail<DT, TOL, K>(t, acc);
   }
@@ -295,8 +347,7 @@ hipError_t launch_fallback(const BlockVoteD &b, int num_cus, hipStream_t s) {
 template <int K>
 hipError_t launch_blocks_k(const BlockVoteD &b, int num_cus, hipStream_t s) {
   const dim3 grid((uint32_t)b.nblocks), block((uint32_t)(b.block_bytes / 64));
-  if constexpr (K <= 5) hipLaunchKernelGGL((k_vote_blocks<K, true>), grid, block, 0, s, b);
-  else hipLaunchKernelGGL((k_vote_blocks<K, false>), grid, block, 0, s, b);
+  hipLaunchKernelGGL((k_vote_blocks<K>), grid, block, 0, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (b.dtype * 3 + b.tolkind) {

@@ -48,10 +48,11 @@ struct TileD {
 constexpr int kMaxGrid = 8192;     // per-task launch: workgroups (partials rows)
 constexpr int kNumCounters = 32;   // >= 21 pairs + 7 disagree + 1 no-majority
 
-// Per-workgroup partial counts of the per-task launch, plus its ticket.
+// Device accumulators of the per-task launch and its ticket; both are left
+// zeroed by the last workgroup of every launch.
 struct VoteWs {
-  uint64_t *partials;  // [kMaxGrid][kNumCounters]
-  uint32_t *ticket;    // self-resetting
+  uint64_t *acc;     // [kNumCounters]
+  uint32_t *ticket;
 };
 
 int elem_size(int dtype);

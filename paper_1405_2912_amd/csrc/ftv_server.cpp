@@ -150,6 +150,7 @@ struct ftv_server {
   int ring_next = 0;
   // statistics
   uint64_t submitted = 0, completed = 0, rejected = 0, iterations = 0, peak_q = 0;
+  uint64_t shared_iters = 0, max_reqs_iter = 0;
   double q_integral = 0;
   int64_t q_last_t = 0, t_first = 0, t_last_done = 0;
   uint64_t replica_bytes_done = 0;
@@ -243,7 +244,7 @@ int launch_iteration(ftv_server *s, Iter &it) {
   uint32_t *hs = reinterpret_cast<uint32_t *>(it.h_buf + 256);
   TileD *ht = reinterpret_cast<TileD *>(it.h_buf + 256 + sizeof(uint32_t) * s->cfg.max_slots);
   const uint64_t chunk_tiles = std::max<uint64_t>(1, s->cfg.chunk_bytes / (16ull * kTileVecs));
-  uint64_t nnew = 0, ntiles = 0;
+  uint64_t nnew = 0, ntiles = 0, nreq = s->fp_wait.size();
   std::vector<uint64_t> still;
   for (uint64_t tk : s->active) {
     Req &r = s->reqs[tk];
@@ -263,6 +264,7 @@ int launch_iteration(ftv_server *s, Iter &it) {
       d.last = (j + 1 == r.ntiles) ? 1u : 0u;
     }
     r.issued += (uint32_t)take;
+    nreq += take ? 1 : 0;
     if (r.issued == r.ntiles) it.finishing.push_back(tk);
     else still.push_back(tk);
   }
@@ -298,6 +300,8 @@ int launch_iteration(ftv_server *s, Iter &it) {
   HIPCHK(hipEventRecord(it.ev, s->stream));
   it.busy = true;
   s->iterations++;
+  if (nreq >= 2) s->shared_iters++;
+  s->max_reqs_iter = std::max<uint64_t>(s->max_reqs_iter, nreq);
   return FTV_OK;
 }
 
@@ -594,6 +598,8 @@ int ftv_server_get_stats(ftv_server *s, ftv_server_stats *out) {
   out->peak_bytes_in_flight = s->peak_bytes;
   out->iterations = s->iterations;
   out->peak_queue_depth = s->peak_q;
+  out->shared_iterations = s->shared_iters;
+  out->max_requests_per_iteration = s->max_reqs_iter;
   const int64_t now = ftv_now_ns();
   double integral = s->q_integral;
   if (s->q_last_t) integral += (double)s->queue.size() * (double)(now - s->q_last_t);

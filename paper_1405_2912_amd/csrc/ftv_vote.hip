@@ -1,9 +1,10 @@
 // ftv_vote.hip -- per-task and batched (persistent) vote kernels for gfx950.
 //
 // Per-task launch: a grid-stride loop over tiles of 16-byte vectors; each
-// workgroup reduces its wave accumulators into one row of partial counts, and
-// the last workgroup to finish (atomic ticket) sums the rows, decides the
-// verdict and writes the whole stats record, then re-arms the ticket.
+// workgroup reduces its wave accumulators and adds the non-zero totals to the
+// launch's device accumulators; the last workgroup to finish (atomic ticket)
+// decides the verdict, writes the whole stats record and re-arms the
+// accumulators and the ticket for the next launch.
 //
 // Batched launch: one persistent grid pulls tiles from an atomic queue over a
 // table of (task, vector range) entries; a tile may belong to any task, so the
@@ -18,6 +19,8 @@ namespace ftv {
 namespace {
 
 using namespace dev;
+
+constexpr int kVoteWgPerCu = 2;
 
 template <int K>
 struct Unroll {
@@ -41,10 +44,12 @@ __global__ __launch_bounds__(256) void k_vote_task(TaskD t, VoteWs ws) {
   if constexpr (VEC) {
     if (blockIdx.x == gridDim.x - 1) vote_tail<DT, TOL, K>(t, acc);
   }
+  // non-zero workgroup totals go into the launch's device accumulators (most
+  // workgroups see no disagreement and add nothing); the last workgroup to
+  // finish reads them, writes the stats record and clears them again
   const uint64_t tot = block_total<K>(acc, sh);
-  if (threadIdx.x < (uint32_t)kNumCounters)
-    ws.partials[(uint64_t)blockIdx.x * kNumCounters + threadIdx.x] =
-        threadIdx.x < (uint32_t)NC ? tot : 0;
+  if (threadIdx.x < (uint32_t)NC && tot != 0)
+    __hip_atomic_fetch_add(&ws.acc[threadIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -55,18 +60,10 @@ __global__ __launch_bounds__(256) void k_vote_task(TaskD t, VoteWs ws) {
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  // last workgroup: rows are summed by groups of 32 threads, one counter each
-  const uint32_t q = threadIdx.x & 31u, g = threadIdx.x >> 5, ng = blockDim.x >> 5;
-  uint64_t s = 0;
-  for (uint32_t row = g; row < gridDim.x; row += ng)
-    s += __hip_atomic_load(&ws.partials[(uint64_t)row * kNumCounters + q], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-  sh[g * kNumCounters + q] = s;
-  __syncthreads();
   if (threadIdx.x < (uint32_t)kNumCounters) {
-    uint64_t v = 0;
-    for (uint32_t gg = 0; gg < ng; ++gg) v += sh[gg * kNumCounters + threadIdx.x];
-    s_tot[threadIdx.x] = v;
+    s_tot[threadIdx.x] =
+        __hip_atomic_load(&ws.acc[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ws.acc[threadIdx.x], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -131,7 +128,7 @@ __global__ __launch_bounds__(512) void k_vote_batch(BatchLaunch b) {
     const uint32_t ti = s_tile;
     if (ti >= ntiles) break;
     const TileD tile = b.tiles[ti];
-    const TaskD t = b.tasks[tile.task];
+    const TaskD &t = b.tasks[tile.task];  // read in place: a copy would go to scratch
     switch (t.spec) {
       FTV_CASES_K(FTV_F32, FTV_TOL_EXACT)
       FTV_CASES_K(FTV_F32, FTV_TOL_ULP)
@@ -195,7 +192,12 @@ hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t
   constexpr int U = Unroll<K>::value;
   const uint64_t tile = 256ull * U;
   uint64_t tiles = (t.nvec + tile - 1) / tile;
-  uint64_t cap = (uint64_t)num_cus * resident_per_cu<DT, TOL, K, VEC>();
+  // two workgroups per CU stream the replicas at the highest rate measured on
+  // MI355X (more concurrent streams lose DRAM page locality); never more than
+  // fit at once
+  const int per_cu = resident_per_cu<DT, TOL, K, VEC>() < kVoteWgPerCu ? resident_per_cu<DT, TOL, K, VEC>()
+                                                                       : kVoteWgPerCu;
+  uint64_t cap = (uint64_t)num_cus * per_cu;
   if (cap > (uint64_t)kMaxGrid) cap = kMaxGrid;
   const uint32_t grid = (uint32_t)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
   hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(256), 0, s, t, ws);

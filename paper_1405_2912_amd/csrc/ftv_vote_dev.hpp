@@ -181,45 +181,60 @@ __device__ __forceinline__ typename VT<DT>::W vote3_general(const typename VT<DT
   return okey_inv<DT>(kc);
 }
 
-// k = 3.  If two replicas are bit-identical their value is the consensus in
-// every case (with the third equal to it all three are candidates and the
-// pair holds the median; otherwise the pair are the only candidates), so one
-// tolerance test -- third against the pair -- decides the element.  Only
-// elements whose three bit patterns all differ take the general path.
-template <int DT, int TOL>
-__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote3(const typename VT<DT>::W (&x)[3],
-                                                             const TolD &t) {
+// Bit mask of the replica pairs (0,1),(0,2),..,(1,2),.. that involve replica r.
+template <int K>
+__device__ __forceinline__ uint32_t pairs_of(uint32_t r) {
+  uint32_t m = 0;
+  int q = 0;
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int j = i + 1; j < K; ++j, ++q) m |= (uint32_t)((uint32_t)i == r || (uint32_t)j == r) << q;
+  return m;
+}
+
+template <int DT, int TOL, int K>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general(const typename VT<DT>::W (&x)[K],
+                                                                    const TolD &t);
+
+// k >= 3.  If all replicas but at most one hold the same bit pattern m, then m
+// is the consensus whatever the odd replica holds: with the odd one equal to m
+// (under the tolerance) all k replicas are candidates and k-1 of them hold m,
+// so the lower median is m; otherwise the k-1 copies of m are the only
+// candidates.  Either way 2(k-1) > k is a majority.  One tolerance test, odd
+// replica against m, decides the element; elements with two or more differing
+// bit patterns take the general computation.
+template <int DT, int TOL, int K>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_fast(const typename VT<DT>::W (&x)[K],
+                                                                 const TolD &t, bool &general) {
   using W = typename VT<DT>::W;
   ElemOut<W> o;
-  const bool i01 = x[0] == x[1], i02 = x[0] == x[2], i12 = x[1] == x[2];
-  const W pv = (i01 | i02) ? x[0] : x[1];
-  const W xt = i01 ? x[2] : (i02 ? x[1] : x[0]);
-  const uint32_t third = i01 ? 2u : (i02 ? 1u : 0u);
-  const bool e = eqv<DT, TOL>(xt, pv, t);
-  // pairs (0,1)=bit0 (0,2)=bit1 (1,2)=bit2 that involve the third replica
-  const uint32_t tpairs = third == 2u ? 6u : (third == 1u ? 5u : 3u);
-  o.cons = pv;
-  o.mb = e ? 0u : (1u << third);
-  o.ne = e ? 0u : tpairs;
-  if (!(i01 | i02 | i12)) {
-    const Pre<DT, TOL> p0 = prep<DT, TOL>(x[0]), p1 = prep<DT, TOL>(x[1]), p2 = prep<DT, TOL>(x[2]);
-    const uint32_t ne = (uint32_t)!eqp<DT, TOL>(p0, p1, t) | ((uint32_t)!eqp<DT, TOL>(p0, p2, t) << 1) |
-                        ((uint32_t)!eqp<DT, TOL>(p1, p2, t) << 2);
-    o.ne = ne;
-    o.cons = vote3_general<DT>(x, ne, o.mb);
+  // with at most one outlier, two of the first three replicas hold m
+  const W m = (x[0] == x[1] || x[0] == x[2]) ? x[0] : x[1];
+  uint32_t nd = 0, odd = 0;
+  W xo = m;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    const bool d = x[r] != m;
+    nd += d ? 1u : 0u;
+    odd = d ? (uint32_t)r : odd;
+    xo = d ? x[r] : xo;
   }
+  const bool e = eqv<DT, TOL>(xo, m, t);  // true when nothing differs
+  o.cons = m;
+  o.mb = e ? 0u : (1u << odd);
+  o.ne = e ? 0u : pairs_of<K>(odd);
+  general = nd > 1u;
   return o;
 }
 
-// Generic k: supports, candidate set, lower median of the candidates by key.
+// General k: supports, candidate set, lower median of the candidates by key.
+// Recomputes keys instead of keeping per-replica arrays, to stay small in
+// registers: it only runs for elements with two or more differing patterns.
 template <int DT, int TOL, int K>
 __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general(const typename VT<DT>::W (&x)[K],
-                                                                 const TolD &t) {
-
+                                                                    const TolD &t) {
   using W = typename VT<DT>::W;
-  Pre<DT, TOL> p[K];
-#pragma unroll
-  for (int r = 0; r < K; ++r) p[r] = prep<DT, TOL>(x[r]);
   uint32_t adj[K];
 #pragma unroll
   for (int r = 0; r < K; ++r) adj[r] = 1u << r;
@@ -229,7 +244,7 @@ __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general(const typena
   for (int r = 0; r < K; ++r) {
 #pragma unroll
     for (int j = r + 1; j < K; ++j, ++q) {
-      const bool e = eqp<DT, TOL>(p[r], p[j], t);
+      const bool e = eqv<DT, TOL>(x[r], x[j], t);
       adj[r] |= (uint32_t)e << j;
       adj[j] |= (uint32_t)e << r;
       ne |= (uint32_t)(!e) << q;
@@ -244,31 +259,25 @@ __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general(const typena
     const W k0 = okey<DT>(x[0]), k1 = okey<DT>(x[1]);
     o.cons = okey_inv<DT>(umin(k0, k1));
     o.mb = ne ? (0x80u | (k0 < k1 ? 2u : 1u)) : 0u;
-  } else if constexpr (K == 3) {
-    o.cons = vote3_general<DT>(x, ne, o.mb);
   } else {
-    int s[K];
     int M = 0;
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-      s[r] = __popc(adj[r]);
-      M = s[r] > M ? s[r] : M;
-    }
+    for (int r = 0; r < K; ++r) M = __popc(adj[r]) > M ? __popc(adj[r]) : M;
     uint32_t cm = 0;
 #pragma unroll
-    for (int r = 0; r < K; ++r) cm |= (uint32_t)(s[r] == M) << r;
+    for (int r = 0; r < K; ++r) cm |= (uint32_t)(__popc(adj[r]) == M) << r;
     const int target = (__popc(cm) - 1) >> 1;
-    W ok[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) ok[r] = okey<DT>(x[r]);
     W cv = x[0];
     uint32_t ac = adj[0];
 #pragma unroll
     for (int r = 0; r < K; ++r) {
+      const W kr = okey<DT>(x[r]);
       int rank = 0;
 #pragma unroll
-      for (int j = 0; j < K; ++j)
-        rank += (int)(((cm >> j) & 1u) && (ok[j] < ok[r] || (ok[j] == ok[r] && j < r)));
+      for (int j = 0; j < K; ++j) {
+        const W kj = okey<DT>(x[j]);
+        rank += (int)(((cm >> j) & 1u) && (kj < kr || (kj == kr && j < r)));
+      }
       if (((cm >> r) & 1u) && rank == target) {
         cv = x[r];
         ac = adj[r];
@@ -280,25 +289,101 @@ __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general(const typena
   return o;
 }
 
-// Vote of one element.  k = 2 and k = 3 have closed forms; larger k skip the
-// general computation when all k bit patterns are identical.
+// rep[r] for a runtime r as a select chain over the seven slots: indexing a
+// by-value record with a runtime index would move it to scratch memory.
+__device__ __forceinline__ const void *rep_sel(const void *const (&rep)[FTV_MAX_K], int r) {
+  const void *p = rep[0];
+#pragma unroll
+  for (int j = 1; j < FTV_MAX_K; ++j) p = (j == r) ? rep[j] : p;
+  return p;
+}
+
+// General vote of element i for a runtime k (4..7): the same definition as
+// vote_general, with loops that are not unrolled, the support relation packed
+// into one 64-bit word (bit 8r+j = eq(x_r, x_j)) and replica values re-read
+// from memory when needed, so that the rare elements that need it cost
+// registers only for their own duration.
+template <int DT, int TOL>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general_dyn(
+    const void *const (&rep)[FTV_MAX_K], int k, uint64_t i, const TolD &t) {
+  using W = typename VT<DT>::W;
+  auto X = [&](int r) -> W { return reinterpret_cast<const W *>(rep_sel(rep, r))[i]; };
+  uint64_t A = 0;
+  uint32_t ne = 0;
+  int q = 0;
+#pragma unroll 1
+  for (int r = 0; r < k; ++r) {
+    const W xr = X(r);
+    A |= 1ull << (8 * r + r);
+#pragma unroll 1
+    for (int j = r + 1; j < k; ++j, ++q) {
+      if (eqv<DT, TOL>(xr, X(j), t)) A |= (1ull << (8 * r + j)) | (1ull << (8 * j + r));
+      else ne |= 1u << q;
+    }
+  }
+  int M = 0;
+#pragma unroll 1
+  for (int r = 0; r < k; ++r) {
+    const int sr = __popcll((A >> (8 * r)) & 0xffull);
+    M = sr > M ? sr : M;
+  }
+  uint32_t cm = 0;
+#pragma unroll 1
+  for (int r = 0; r < k; ++r) cm |= (uint32_t)(__popcll((A >> (8 * r)) & 0xffull) == M) << r;
+  const int target = (__popc(cm) - 1) >> 1;
+  int c = 0;
+#pragma unroll 1
+  for (int r = 0; r < k; ++r) {
+    if (!((cm >> r) & 1u)) continue;
+    const W kr = okey<DT>(X(r));
+    int rank = 0;
+#pragma unroll 1
+    for (int j = 0; j < k; ++j) {
+      if (!((cm >> j) & 1u)) continue;
+      const W kj = okey<DT>(X(j));
+      rank += (int)(kj < kr || (kj == kr && j < r));
+    }
+    if (rank == target) c = r;
+  }
+  ElemOut<W> o;
+  o.cons = X(c);
+  o.mb = ((uint32_t)~(A >> (8 * c)) & ((1u << k) - 1u)) | (2 * M > k ? 0u : 0x80u);
+  o.ne = ne;
+  return o;
+}
+
+// Elements with two or more differing bit patterns (k >= 3).
+template <int DT, int TOL, int K>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_slow(const typename VT<DT>::W (&x)[K],
+                                                                 const TolD &t,
+                                                                 const void *const (&rep)[FTV_MAX_K],
+                                                                 uint64_t i) {
+  if constexpr (K == 3) {
+    ElemOut<typename VT<DT>::W> o;
+    const uint32_t ne = (uint32_t)!eqv<DT, TOL>(x[0], x[1], t) |
+                        ((uint32_t)!eqv<DT, TOL>(x[0], x[2], t) << 1) |
+                        ((uint32_t)!eqv<DT, TOL>(x[1], x[2], t) << 2);
+    o.ne = ne;
+    o.cons = vote3_general<DT>(x, ne, o.mb);
+    return o;
+  } else {
+    return vote_general_dyn<DT, TOL>(rep, K, i, t);
+  }
+}
+
+// Vote of one element.  k = 2 is one tolerance test; k >= 3 takes the
+// at-most-one-outlier form and falls back to the general computation.
 template <int DT, int TOL, int K>
 __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_elem(const typename VT<DT>::W (&x)[K],
-                                                                 const TolD &t) {
-  using W = typename VT<DT>::W;
-  if constexpr (K == 3) {
-    return vote3<DT, TOL>(x, t);
-  } else if constexpr (K == 2) {
+                                                                 const TolD &t,
+                                                                 const void *const (&rep)[FTV_MAX_K],
+                                                                 uint64_t i) {
+  if constexpr (K == 2) {
     return vote_general<DT, TOL, 2>(x, t);
   } else {
-    bool same = true;
-#pragma unroll
-    for (int r = 1; r < K; ++r) same = same & (x[r] == x[0]);
-    ElemOut<W> o;
-    o.cons = x[0];
-    o.mb = 0;
-    o.ne = 0;
-    if (!same) o = vote_general<DT, TOL, K>(x, t);
+    bool general;
+    ElemOut<typename VT<DT>::W> o = vote_fast<DT, TOL, K>(x, t, general);
+    if (general) o = vote_slow<DT, TOL, K>(x, t, rep, i);
     return o;
   }
 }
@@ -419,6 +504,9 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
         }
       }
     }
+    // fast pass: every element is voted and stored; elements whose replicas
+    // hold two or more differing bit patterns are flagged in `need`
+    uint32_t need = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t vi = base + (uint64_t)u * nth + tid;
@@ -430,10 +518,15 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
         W xe[K];
 #pragma unroll
         for (int r = 0; r < K; ++r) xe[r] = x[u][r][e];
-        const ElemOut<W> o = vote_elem<DT, TOL, K>(xe, t.tol);
+        bool general = false;
+        ElemOut<W> o;
+        if constexpr (K == 2) o = vote_general<DT, TOL, 2>(xe, t.tol);
+        else o = vote_fast<DT, TOL, K>(xe, t.tol, general);
+        general = general && valid;
+        need |= (uint32_t)general << (u * V + e);
         cv[e] = o.cons;
         mbs |= o.mb << (8 * e);
-        acc.add(valid, o.ne, o.mb);
+        acc.add(valid && !general, o.ne, o.mb);
       }
       if (valid) {
         if constexpr (VEC) {
@@ -445,6 +538,30 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
         } else {
           if (wc) st_nt(reinterpret_cast<W *>(t.cons) + vi, cv[0], nt);
           if (wm) t.mask[vi] = (uint8_t)mbs;
+        }
+      }
+    }
+    // fix-up pass (rare): the loaded vectors are dead here, so the general
+    // vote does not add to the register footprint of the fast pass.  The
+    // element is reloaded, voted and stored again after this lane's earlier
+    // stores have completed.
+    if constexpr (K >= 3) {
+      if (__ballot(need != 0u) != 0ull) {
+        __threadfence_block();
+#pragma unroll 1
+        for (int q = 0; q < U * V; ++q) {
+          const bool mine = (need >> q) & 1u;
+          ElemOut<W> o{};
+          if (mine) {
+            const uint64_t i = (base + (uint64_t)(q / V) * nth + tid) * V + (uint64_t)(q % V);
+            W xe[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r) xe[r] = reinterpret_cast<const W *>(t.rep[r])[i];
+            o = vote_slow<DT, TOL, K>(xe, t.tol, t.rep, i);
+            if (wc) reinterpret_cast<W *>(t.cons)[i] = o.cons;
+            if (wm) t.mask[i] = (uint8_t)o.mb;
+          }
+          acc.add(mine, o.ne, o.mb);
         }
       }
     }
@@ -461,7 +578,7 @@ __device__ __forceinline__ void vote_tail(const TaskD &t, Acc<K> &acc) {
   W xe[K];
 #pragma unroll
   for (int r = 0; r < K; ++r) xe[r] = valid ? reinterpret_cast<const W *>(t.rep[r])[i] : (W)0;
-  const ElemOut<W> o = vote_elem<DT, TOL, K>(xe, t.tol);
+  const ElemOut<W> o = vote_elem<DT, TOL, K>(xe, t.tol, t.rep, valid ? i : 0);
   acc.add(valid, o.ne, o.mb);
   if (valid) {
     if (t.cons) reinterpret_cast<W *>(t.cons)[i] = o.cons;

@@ -83,7 +83,8 @@ class ServerStats(Structure):
     _fields_ = [("submitted", c_uint64), ("completed", c_uint64), ("queued", c_uint64),
                 ("in_flight", c_uint64), ("rejected", c_uint64), ("bytes_in_flight", c_uint64),
                 ("peak_bytes_in_flight", c_uint64), ("iterations", c_uint64),
-                ("peak_queue_depth", c_uint64), ("mean_queue_depth", c_double),
+                ("peak_queue_depth", c_uint64), ("shared_iterations", c_uint64),
+                ("max_requests_per_iteration", c_uint64), ("mean_queue_depth", c_double),
                 ("p50_us", c_double), ("p99_us", c_double), ("mean_us", c_double),
                 ("max_us", c_double), ("replica_gbps", c_double)]
 

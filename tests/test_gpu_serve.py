@@ -54,10 +54,10 @@ def test_alone_equals_mix_equals_oracle(gpu):
     reqs = _requests(gpu, rng, 48, 400000)
     torch.cuda.synchronize()
     srv = gpu.Server(hbm_budget_bytes=8 << 30, chunk_bytes=256 << 10, max_slots=64)
-    # the mix: Poisson arrivals at ~2000/s, submitted as they "arrive"
+    # the mix: Poisson arrivals at ~10000/s, submitted as they "arrive"
     print("case: serving mix of 48 requests", flush=True)
     t0 = gpu.now_ns()
-    arrivals = t0 + np.cumsum(rng.exponential(500e3, len(reqs))).astype(np.int64)
+    arrivals = t0 + np.cumsum(rng.exponential(100e3, len(reqs))).astype(np.int64)
     tickets = []
     for r, ta in zip(reqs, arrivals):
         while gpu.now_ns() < ta:
@@ -66,7 +66,9 @@ def test_alone_equals_mix_equals_oracle(gpu):
         tickets.append(srv.submit_vote(r["t"], r["tol_f"], c, m, t_arrival_ns=int(ta), n=r["n"]))
     mix = [srv.poll(tk, -1) for tk in tickets]
     st = srv.stats()
-    assert st["completed"] == len(reqs) and st["iterations"] < len(reqs)
+    # requests that arrived while others were on the GPU shared launches with them
+    assert st["completed"] == len(reqs) and st["shared_iterations"] >= 1
+    assert st["max_requests_per_iteration"] >= 2
     # overlap: some request was admitted before another one finished
     spans = sorted((res.t_admit_ns, res.t_done_ns) for res in mix)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
