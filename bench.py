@@ -74,7 +74,7 @@ def main_vote(ftv, ctx, steps, warmup, side):
     import synth.device as sd
     n = side * side
     log(f"bench: generating k=3 fp32 {side}x{side} replicas on the device")
-    reps = sd.config2(n, "f32")
+    reps = sd.large_task_set(n, "f32")
     cons = torch.empty_like(reps[0])
     mask = torch.empty(n, dtype=torch.uint8, device=reps[0].device)
     st = ftv.stats_tensor(reps[0].device)
@@ -250,7 +250,7 @@ def bench_blocks(ftv, ctx, side=16384, reps_timed=10):
     import synth.device as sd
     n = side * side
     log(f"bench: generating the k=5 fp64 {side}x{side} checkpoint replicas")
-    reps = sd.config5(n)
+    reps = sd.checkpoint_set(n)
     per = 8192
     fb = 4321 % (n // per)
     reps[1][fb * per + 3] = 0.0
@@ -290,7 +290,7 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0):
     import synth.device as sd
     pool_elems = (256 << 20) // 4
     log("bench: serving pool (3 x 256 MiB fp32 replicas with the large-task faults)")
-    pool = sd.config2(pool_elems, "f32", flip_rate=1e-7 * 64)
+    pool = sd.large_task_set(pool_elems, "f32", flip_rate=1e-7 * 64)
     srv = ftv.Server(hbm_budget_bytes=64 << 30, arena_bytes=24 << 30, chunk_bytes=32 << 20,
                      max_slots=1024, max_queue=1 << 20)
     rng = np.random.default_rng(14052912 + 4)

@@ -299,6 +299,37 @@ int ftv_server_get_stats(ftv_server *srv, ftv_server_stats *out);
 /* Drains in-flight work, then stops the server thread and frees everything. */
 int ftv_server_destroy(ftv_server *srv);
 
+/* ---- fault-aware runtime estimation (Sec. IV-B) --------------------------- *
+ * A processing unit i with fault-free runtime R_i that produced v_i valid
+ * results out of t_i runs has fault probability p_i = 1 - v_i/t_i (the paper
+ * prints p_i = v_i/t_i while calling it the fault probability; its worked
+ * numbers -- a unit twice as fast is worth keeping below 50%, p = 0.75 gives
+ * four times the runtime, a unit three times as fast loses from 66% on --
+ * fix this reading) and fault-aware runtime F_i = R_i / (1 - p_i), the
+ * expected time until the unit returns a correct result.  F_i is +infinity
+ * when p_i = 1; such a unit is only re-tried at check intervals. */
+typedef struct ftv_unit {
+  double runtime;   /* R_i: fault-free runtime (any unit, > 0) */
+  uint64_t valid;   /* v_i */
+  uint64_t total;   /* t_i (0 = no history: F_i = R_i) */
+} ftv_unit;
+
+/* F_i of one unit; +infinity when valid == 0 < total; NaN for bad input
+ * (runtime <= 0 or valid > total). */
+double ftv_fault_aware_runtime(const ftv_unit *unit);
+/* Order (host array of n indices) of the units by increasing F_i, ties by
+ * lower index; units with F_i = +infinity come last unless `probe` is set, in
+ * which case the first of them is moved to the front (the periodic re-check
+ * of a unit that looked permanently faulty).  FTV_E_INVALID on bad input. */
+int ftv_rank_units(const ftv_unit *units, uint32_t n, int probe, uint32_t *order);
+/* Account one voted task: replica r was produced by unit unit_of_replica[r]
+ * (host arrays; `stats` is a HOST copy of the task's ftv_stats).  A replica's
+ * run is valid when it agrees with the consensus on every element
+ * (disagree[r] == 0).  An UNRESOLVED vote decides nothing and changes no
+ * counter (the task is re-executed). */
+int ftv_record_vote(ftv_unit *units, uint32_t nunits, const uint32_t *unit_of_replica, uint32_t k,
+                    const ftv_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

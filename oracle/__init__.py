@@ -70,6 +70,8 @@ def lib():
         L.fto_vote_blocks.argtypes = [i32, i32, u64, vp, i32, u64, dbl, dbl, u64,
                                       vp, vp, vp, vp, vp, vp]
         L.fto_vote_blocks.restype = i32
+        L.fto_fault_aware_runtime.argtypes = [dbl, u64, u64]
+        L.fto_fault_aware_runtime.restype = dbl
         _lib = L
     return _lib
 
@@ -223,3 +225,8 @@ def vote_blocks(replicas, tol: Tol, block_bytes: int = 65536) -> BlockVoteResult
         raise ValueError(f"oracle block vote rejected arguments (code {rc})")
     return BlockVoteResult(fps, bmap, cons, mask, int(bst[0]), int(bst[1]), int(bst[2]),
                            int(bst[3]), bst[4:4 + k].copy(), int(vw[0]), int(vw[1]))
+
+
+def fault_aware_runtime(runtime: float, valid: int, total: int) -> float:
+    """F = R / (1 - p) with p = 1 - valid/total (Sec. IV-B)."""
+    return float(lib().fto_fault_aware_runtime(float(runtime), int(valid), int(total)))

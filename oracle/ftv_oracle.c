@@ -449,3 +449,14 @@ int fto_vote_blocks(int dt, int k, uint64_t nbytes, const void *const *reps, int
   }
   return 0;
 }
+
+/* ---- exported: fault-aware runtime (Sec. IV-B) -----------------------------
+ * p = 1 - v/t is the fault probability of a unit with v valid runs out of t;
+ * F = R / (1 - p) = R * (t / v): the fault-free runtime scaled by the
+ * expected number of runs until one is valid.  No history (t = 0): F = R.
+ * v = 0 < t: p = 1, F = +infinity. */
+double fto_fault_aware_runtime(double R, uint64_t v, uint64_t t) {
+  if (t == 0) return R;
+  if (v == 0) return INFINITY;
+  return R * ((double)t / (double)v);
+}

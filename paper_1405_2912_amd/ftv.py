@@ -89,11 +89,15 @@ class ServerStats(Structure):
                 ("max_us", c_double), ("replica_gbps", c_double)]
 
 
+class Unit(Structure):
+    _fields_ = [("runtime", c_double), ("valid", c_uint64), ("total", c_uint64)]
+
+
 EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv_ctx_destroy",
            "ftv_vote", "ftv_vote_batch", "ftv_batch_get_config", "ftv_batch_set_config",
            "ftv_tune_batch", "ftv_fingerprint", "ftv_vote_blocks", "ftv_server_create",
            "ftv_submit", "ftv_poll", "ftv_release", "ftv_server_get_stats",
-           "ftv_server_destroy"]
+           "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote"]
 
 _lib = None
 
@@ -128,10 +132,15 @@ def load():
         L.ftv_release.argtypes = [vp, c_uint64]
         L.ftv_server_get_stats.argtypes = [vp, POINTER(ServerStats)]
         L.ftv_server_destroy.argtypes = [vp]
+    L.ftv_fault_aware_runtime.argtypes = [POINTER(Unit)]
+    L.ftv_rank_units.argtypes = [POINTER(Unit), c_uint32, c_int, POINTER(c_uint32)]
+    L.ftv_record_vote.argtypes = [POINTER(Unit), c_uint32, POINTER(c_uint32), c_uint32, POINTER(Stats)]
     for name in EXPORTS:
         fn = getattr(L, name, None)
-        if fn is not None and name not in ("ftv_version", "ftv_last_error", "ftv_now_ns"):
+        if fn is not None and name not in ("ftv_version", "ftv_last_error", "ftv_now_ns",
+                                           "ftv_fault_aware_runtime"):
             fn.restype = c_int
+    L.ftv_fault_aware_runtime.restype = c_double
     _lib = L
     return L
 
@@ -397,3 +406,22 @@ def result_stats(res: Result) -> dict:
     return {"pair": np.array(s.pair, dtype=np.uint64).reshape(7, 7),
             "disagree": np.array(s.disagree, dtype=np.uint64), "no_majority": int(s.no_majority),
             "n": int(s.n), "verdict": int(s.verdict), "winner": int(s.winner)}
+
+
+# ---- fault-aware runtime estimation ------------------------------------------
+def fault_aware_runtime(unit: Unit) -> float:
+    return float(load().ftv_fault_aware_runtime(ctypes.byref(unit)))
+
+
+def rank_units(units, probe: bool = False):
+    arr = (Unit * len(units))(*units)
+    order = (c_uint32 * len(units))()
+    _check(load().ftv_rank_units(arr, len(units), int(probe), order))
+    return list(order)
+
+
+def record_vote(units, unit_of_replica, stats: Stats):
+    """units: a ctypes array of Unit (updated in place); stats: a host Stats."""
+    k = len(unit_of_replica)
+    u = (c_uint32 * k)(*unit_of_replica)
+    _check(load().ftv_record_vote(units, len(units), u, k, ctypes.byref(stats)))

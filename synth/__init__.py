@@ -153,7 +153,7 @@ def flip_bits(a: np.ndarray, pos: np.ndarray, bits: np.ndarray) -> None:
 # --------------------------------------------------------------------------
 # replica-set recipes at host scale (the device twin builds the large ones)
 # --------------------------------------------------------------------------
-def config1(n: int = 1 << 20, seed: int = SEED_BASE + 1):
+def small_task_set(n: int = 1 << 20, seed: int = SEED_BASE + 1):
     """k=3 fp32: replica 1 has +-1..2 ULP on 10% of elements, replica 2 has 16
     single-bit flips.  Tolerance 4 ULP."""
     base = values("f32", UNIFORM, seed, 0, n)
@@ -165,7 +165,7 @@ def config1(n: int = 1 << 20, seed: int = SEED_BASE + 1):
     return [base, r1, r2]
 
 
-def config2(n: int, dtype: str = "f32", seed: int = SEED_BASE + 2, flip_rate: float = 1e-7,
+def large_task_set(n: int, dtype: str = "f32", seed: int = SEED_BASE + 2, flip_rate: float = 1e-7,
             zero_block_elems: int = None):
     """k=3: replica 1 has +-1 ULP on 30%; replica 2 has one 4 KiB block set to
     +0 and round(rate*n) single-bit flips."""
@@ -184,7 +184,7 @@ def config2(n: int, dtype: str = "f32", seed: int = SEED_BASE + 2, flip_rate: fl
     return [base, r1, r2]
 
 
-def config5(n: int, seed: int = SEED_BASE + 5, nstuck: int = 256, nflip: int = None,
+def checkpoint_set(n: int, seed: int = SEED_BASE + 5, nstuck: int = 256, nflip: int = None,
             flip_rate: float = 1e-7):
     """k=5 fp64 checkpoint: r0, r4 clean; r1 with stuck-at-0 words; r2 with bit
     flips; r3 rotated right by one element."""

@@ -93,9 +93,9 @@ def flip_bits(t, pos: np.ndarray, bits: np.ndarray):
     iv[p] = torch.bitwise_xor(iv[p], masks)
 
 
-def config2(n: int, dtype: str = "f32", seed: int = SEED_BASE + 2, device="cuda",
+def large_task_set(n: int, dtype: str = "f32", seed: int = SEED_BASE + 2, device="cuda",
             flip_rate: float = 1e-7):
-    """Device version of synth.config2 (same values, same faults)."""
+    """Device version of synth.large_task_set (same values, same faults)."""
     import torch
     td = _torch_dtype(dtype)
     base = torch.empty(n, dtype=td, device=device)
@@ -114,9 +114,9 @@ def config2(n: int, dtype: str = "f32", seed: int = SEED_BASE + 2, device="cuda"
     return [base, r1, r2]
 
 
-def config5(n: int, seed: int = SEED_BASE + 5, device="cuda", nstuck: int = 256, nflip=None,
+def checkpoint_set(n: int, seed: int = SEED_BASE + 5, device="cuda", nstuck: int = 256, nflip=None,
             flip_rate: float = 1e-7):
-    """Device version of synth.config5."""
+    """Device version of synth.checkpoint_set."""
     import torch
     base = torch.empty(n, dtype=torch.float64, device=device)
     fill(base, "f64", NORMAL, seed, 0)

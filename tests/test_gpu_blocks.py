@@ -61,15 +61,15 @@ def _hold(ctx):
     yield
 
 
-def test_config5_recipe_reduced(gpu):
+def test_checkpoint_recipe_reduced(gpu):
     n = 1 << 19   # 4 MiB per replica, 64 blocks of 64 KiB
-    reps = synth.config5(n, nstuck=40, nflip=20)
+    reps = synth.checkpoint_set(n, nstuck=40, nflip=20)
     base = reps[0]
     # forced: a stuck word (r1) and a flip (r2) in the same block -> no majority
     b = 17 * 8192
     reps[1][b + 5] = 0.0
     reps[2].view(np.uint64)[b + 900] ^= np.uint64(1 << 51)
-    print("case: config-5 recipe, 2^19 fp64, k=5", flush=True)
+    print("case: checkpoint recipe, 2^19 fp64, k=5", flush=True)
     ref = _block_case(gpu, reps, oracle.exact(), gpu.exact(), 65536)
     assert ref.fallback_blocks >= 1 and np.array_equal(ref.consensus.view(np.uint64), base.view(np.uint64))
 
@@ -103,7 +103,7 @@ def test_block_vote_empty_and_tiny(gpu):
         _block_case(gpu, reps, oracle.exact(), gpu.exact(), 4096)
 
 
-def test_config5_full_size(gpu):
+def test_checkpoint_full_size(gpu):
     """k=5 fp64 16384x16384 checkpoint: every fault-carrying block plus a random
     sample of blocks checked against the oracle, and the block-level counts
     against the fault plan."""
@@ -112,8 +112,8 @@ def test_config5_full_size(gpu):
     n = 16384 * 16384
     bb = 65536
     per = bb // 8
-    print("case: config-5 full size", flush=True)
-    reps = sd.config5(n)
+    print("case: checkpoint full size", flush=True)
+    reps = sd.checkpoint_set(n)
     fb = 4321
     reps[1][fb * per + 3] = 0.0                       # forced no-majority block
     iv = reps[2].view(torch.int64)

@@ -104,7 +104,7 @@ def test_server_owned_outputs_and_fingerprints(gpu):
     rng = np.random.default_rng(5)
     ctx = gpu.Context(0)
     srv = gpu.Server(hbm_budget_bytes=1 << 30, arena_bytes=256 << 20, chunk_bytes=1 << 20, max_slots=8)
-    reps = synth.config1(n=(1 << 20) + 3)
+    reps = synth.small_task_set(n=(1 << 20) + 3)
     t = [torch.from_numpy(r).cuda() for r in reps]
     tk = srv.submit_vote(t, gpu.ulp(4))
     raw = rng.integers(0, 256, 3 * 65536 + 100, dtype=np.uint8)

@@ -97,11 +97,11 @@ def ctx(gpu):
     c.close()
 
 
-def test_config1_full(gpu, ctx):
-    print("case: config-1 full, n=2^20 k=3 fp32 ULP4", flush=True)
-    reps = synth.config1()
+def test_small_task_set(gpu, ctx):
+    print("case: small task set, n=2^20 k=3 fp32 ULP4", flush=True)
+    reps = synth.small_task_set()
     ref = oracle.vote(reps, oracle.ulp(4))
-    _check(_run(gpu, ctx, reps, gpu.ulp(4)), ref, 3, "config1")
+    _check(_run(gpu, ctx, reps, gpu.ulp(4)), ref, 3, "small_task_set")
     assert ref.verdict == oracle.TASK_MAJORITY and ref.disagree[2] > 0
 
 
@@ -148,7 +148,7 @@ def test_optional_outputs(gpu, ctx):
 
 
 def test_repeat_is_deterministic(gpu, ctx):
-    reps = synth.config1(n=300001)
+    reps = synth.small_task_set(n=300001)
     a = _run(gpu, ctx, reps, gpu.ulp(4))
     b = _run(gpu, ctx, reps, gpu.ulp(4))
     assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32)) and np.array_equal(a[1], b[1])
@@ -180,13 +180,13 @@ def test_invalid_arguments_are_errors(gpu, ctx):
     assert e.value.code == gpu.E_INVALID
 
 
-def test_config2_reduced_host_generated(gpu, ctx):
+def test_large_task_recipe_host_generated(gpu, ctx):
     for dtype, tol in (("f32", 4), ("f64", 2)):
         n = 1 << 20
-        print(f"case: config-2 recipe {dtype} n=2^20", flush=True)
-        reps = synth.config2(n, dtype, flip_rate=2e-5)
+        print(f"case: large-task recipe {dtype} n=2^20", flush=True)
+        reps = synth.large_task_set(n, dtype, flip_rate=2e-5)
         ref = oracle.vote(reps, oracle.ulp(tol))
-        _check(_run(gpu, ctx, reps, gpu.ulp(tol)), ref, 3, f"config2 {dtype}")
+        _check(_run(gpu, ctx, reps, gpu.ulp(tol)), ref, 3, f"large_task_set {dtype}")
         assert ref.disagree[2] > 0 and ref.disagree[0] == 0 and ref.disagree[1] == 0
 
 
@@ -207,26 +207,26 @@ def test_device_generator_matches_host_generator(gpu):
         sd.ulp_noise(t, dtype, 3, 1, round(0.3 * (1 << 24)), 3)
         synth.ulp_noise(host, 3, 1, round(0.3 * (1 << 24)), 3)
         assert np.array_equal(t.cpu().numpy().view(U[host.dtype]), host.view(U[host.dtype]))
-    a = sd.config2(1 << 16, "f32")
-    b = synth.config2(1 << 16, "f32")
+    a = sd.large_task_set(1 << 16, "f32")
+    b = synth.large_task_set(1 << 16, "f32")
     for x, y in zip(a, b):
         assert np.array_equal(x.cpu().numpy().view(np.uint32), y.view(np.uint32))
 
 
 @pytest.mark.parametrize("dtype,side,tol", [("f32", 16384, 4), ("f64", 8192, 2)])
-def test_config2_full_size(gpu, ctx, dtype, side, tol):
+def test_large_task_full_size(gpu, ctx, dtype, side, tol):
     """The full single-large-task workload, in the launch configuration the
     benchmark times, checked element by element against the oracle."""
     import torch
     import synth.device as sd
     n = side * side
-    print(f"case: config-2 full size {dtype} {side}x{side}", flush=True)
-    reps_d = sd.config2(n, dtype)
+    print(f"case: large task full size {dtype} {side}x{side}", flush=True)
+    reps_d = sd.large_task_set(n, dtype)
     cons, mask, st = gpu.vote(ctx, reps_d, gpu.ulp(tol))
     torch.cuda.synchronize()
     s = gpu.read_stats(st)
     reps = [r.cpu().numpy() for r in reps_d]
     del reps_d
     ref = oracle.vote(reps, oracle.ulp(tol))
-    _check((cons.cpu().numpy(), mask.cpu().numpy(), s), ref, 3, f"config2 full {dtype}")
+    _check((cons.cpu().numpy(), mask.cpu().numpy(), s), ref, 3, f"large_task_set full {dtype}")
     assert s["verdict"] == gpu.TASK_MAJORITY and s["winner"] == 0

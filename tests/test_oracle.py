@@ -293,7 +293,7 @@ def test_non_transitive_chain():
 
 
 def test_count_identities_and_ulp_pairs_by_walk():
-    reps = synth.config1(n=4096)
+    reps = synth.small_task_set(n=4096)
     res = oracle.vote(reps, oracle.ulp(4))
     pop = np.unpackbits((res.mask & 0x7F)[:, None], axis=1).sum()
     assert res.disagree.sum() == pop
@@ -306,7 +306,7 @@ def test_count_identities_and_ulp_pairs_by_walk():
         for x, y in zip(a[a.view(np.uint32) != b.view(np.uint32)], b[a.view(np.uint32) != b.view(np.uint32)]):
             far += _nextafter_steps(x, y, np.float32, 4) is None
         assert res.pair[i, j] == far
-    # config-1 faults: every flip that left the 4-ULP window is flagged in replica 2
+    # small-task-set faults: every flip that left the 4-ULP window is flagged in replica 2
     assert res.disagree[0] == 0 and res.disagree[1] == 0
     assert res.verdict == oracle.TASK_MAJORITY and res.winner == 0
 
@@ -439,9 +439,9 @@ def test_block_vote_identical_replicas():
     assert np.array_equal(res.consensus.view(np.uint64), a.view(np.uint64))
 
 
-def test_block_vote_config5_shape():
+def test_block_vote_checkpoint_shape():
     n = 64 * 512   # 64 blocks of 4 KiB
-    reps = synth.config5(n, nstuck=9, nflip=7)
+    reps = synth.checkpoint_set(n, nstuck=9, nflip=7)
     base = reps[0]
     res = oracle.vote_blocks(reps, oracle.exact(), 4096)
     per = 4096 // 8
@@ -458,7 +458,7 @@ def test_block_vote_config5_shape():
 
 def test_block_vote_no_majority_falls_back_to_element_vote():
     n = 8 * 512
-    reps = synth.config5(n, nstuck=1, nflip=1)
+    reps = synth.checkpoint_set(n, nstuck=1, nflip=1)
     base = reps[0]
     # force a stuck word (r1) and a flip (r2) into block 3 -> 2 of 5 agree there
     reps[1] = base.copy()
