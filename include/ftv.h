@@ -158,8 +158,9 @@ typedef struct ftv_batch_cfg {
   uint32_t tile_vecs;  /* 16-byte vectors per replica per tile (multiple of block) */
   uint32_t block;      /* threads per workgroup: 256 or 512 */
   uint32_t grid_mult;  /* workgroups per compute unit */
-  uint32_t order;      /* 0 = task order, 1 = largest task first (LPT),
-                          2 = tiles interleaved round-robin across tasks */
+  uint32_t order;      /* tiles are handed out task by task in this order:
+                          0 = as given, 1 = largest task first (LPT),
+                          2 = smallest task first */
   uint32_t nt_stores;  /* 1 = non-temporal stores for consensus and mask */
   uint32_t reserved;
 } ftv_batch_cfg;

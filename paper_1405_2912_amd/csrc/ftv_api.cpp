@@ -109,8 +109,8 @@ struct ftv_ctx {
   uint32_t *ticket = nullptr;
   // batched launch
   ftv_batch_cfg cfg{};
-  uint64_t cap_tasks = 0, cap_tiles = 0;
-  char *d_tab = nullptr;   // [hdr 256 B][TaskD x cap_tasks][TileD x cap_tiles]
+  uint64_t cap_tasks = 0;
+  char *d_tab = nullptr;   // [hdr 256 B][prefix u64 x (cap_tasks+1)][TaskD x cap_tasks]
   char *h_tab = nullptr;   // pinned staging of the same layout
   uint64_t *d_acc = nullptr;
   uint32_t *d_done = nullptr;
@@ -140,9 +140,9 @@ int cfg_check(const ftv_batch_cfg &c) {
   return FTV_OK;
 }
 
-size_t tab_bytes(uint64_t tasks, uint64_t tiles) {
-  return 256 + sizeof(TaskD) * tasks + sizeof(TileD) * tiles;
-}
+size_t prefix_off() { return 256; }
+size_t tasks_off(uint64_t cap) { return (256 + 8 * (cap + 1) + 255) / 256 * 256; }
+size_t tab_bytes(uint64_t cap) { return tasks_off(cap) + sizeof(TaskD) * cap; }
 
 void free_batch(ftv_ctx *c) {
   if (c->gvalid) {
@@ -158,18 +158,17 @@ void free_batch(ftv_ctx *c) {
   c->h_tab = nullptr;
   c->d_acc = nullptr;
   c->d_done = nullptr;
-  c->cap_tasks = c->cap_tiles = 0;
+  c->cap_tasks = 0;
 }
 
-int ensure_capacity(ftv_ctx *c, uint64_t tasks, uint64_t tiles, hipStream_t s) {
-  if (tasks <= c->cap_tasks && tiles <= c->cap_tiles) return FTV_OK;
+int ensure_capacity(ftv_ctx *c, uint64_t tasks, hipStream_t s) {
+  if (tasks <= c->cap_tasks) return FTV_OK;
   // the old buffers may still be read by queued work
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipDeviceSynchronize());
   free_batch(c);
-  uint64_t nt = std::max<uint64_t>(tasks + tasks / 2, 1024);
-  uint64_t nl = std::max<uint64_t>(tiles + tiles / 2, 16384);
-  const size_t tb = tab_bytes(nt, nl);
+  const uint64_t nt = std::max<uint64_t>(tasks + tasks / 2, 1024);
+  const size_t tb = tab_bytes(nt);
   if (hipMalloc(&c->d_tab, tb) != hipSuccess || hipHostMalloc(&c->h_tab, tb) != hipSuccess ||
       hipMalloc(&c->d_acc, sizeof(uint64_t) * kNumCounters * nt) != hipSuccess ||
       hipMalloc(&c->d_done, sizeof(uint32_t) * nt) != hipSuccess) {
@@ -178,14 +177,14 @@ int ensure_capacity(ftv_ctx *c, uint64_t tasks, uint64_t tiles, hipStream_t s) {
     return fail(FTV_E_NOMEM, "cannot allocate the batch tables");
   }
   c->cap_tasks = nt;
-  c->cap_tiles = nl;
   return FTV_OK;
 }
 
 BatchLaunch make_launch(ftv_ctx *c, uint32_t grid) {
   BatchLaunch b;
-  b.tasks = reinterpret_cast<const TaskD *>(c->d_tab + 256);
-  b.tiles = reinterpret_cast<const TileD *>(c->d_tab + 256 + sizeof(TaskD) * c->cap_tasks);
+  b.tasks = reinterpret_cast<const TaskD *>(c->d_tab + tasks_off(c->cap_tasks));
+  b.tiles = nullptr;
+  b.prefix = reinterpret_cast<const uint64_t *>(c->d_tab + prefix_off());
   b.ntiles_dev = reinterpret_cast<const uint64_t *>(c->d_tab);
   b.acc = c->d_acc;
   b.task_done = c->d_done;
@@ -193,6 +192,7 @@ BatchLaunch make_launch(ftv_ctx *c, uint32_t grid) {
   b.block = c->cfg.block;
   b.grid = grid;
   b.nt_stores = c->cfg.nt_stores;
+  b.tile_vecs = c->cfg.tile_vecs;
   return b;
 }
 
@@ -227,11 +227,11 @@ int ensure_graph(ftv_ctx *c, uint32_t grid) {
   return FTV_OK;
 }
 
-// Build the device task records and the ordered tile table in pinned staging.
+// Order the task records by the schedule and write them with the prefix sum
+// of their tile counts into pinned staging, then upload (O(tasks) host work).
 int build_tables(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStream_t s,
                  uint64_t *ntiles_out) {
   std::vector<TaskD> tasks(ntasks);
-  uint64_t ntiles = 0;
   const uint64_t tv = c->cfg.tile_vecs;
   for (uint64_t i = 0; i < ntasks; ++i) {
     int rc = make_task(&descs[i], true, &tasks[i]);
@@ -239,51 +239,37 @@ int build_tables(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStr
     const uint64_t nt = std::max<uint64_t>(1, (tasks[i].nvec + tv - 1) / tv);
     if (nt > 0xffffffffull) return fail(FTV_E_INVALID, "task too large for one batch");
     tasks[i].ntiles = (uint32_t)nt;
-    ntiles += nt;
   }
-  if (ntasks > 0xffffffffull || ntiles > 0xffffffffull)
-    return fail(FTV_E_INVALID, "batch too large");
-  int rc = ensure_capacity(c, ntasks, ntiles, s);
+  if (ntasks > 0xffffffffull) return fail(FTV_E_INVALID, "batch too large");
+  int rc = ensure_capacity(c, ntasks, s);
   if (rc) return rc;
   if (c->staged_pending) {  // the previous upload must have left the staging
     HIPCHK(hipEventSynchronize(c->staged));
     c->staged_pending = false;
   }
-  uint64_t *hdr = reinterpret_cast<uint64_t *>(c->h_tab);
-  hdr[0] = ntiles;
-  hdr[1] = ntasks;
-  TaskD *ht = reinterpret_cast<TaskD *>(c->h_tab + 256);
-  TileD *hl = reinterpret_cast<TileD *>(c->h_tab + 256 + sizeof(TaskD) * c->cap_tasks);
-  memcpy(ht, tasks.data(), sizeof(TaskD) * ntasks);
   std::vector<uint32_t> ord(ntasks);
   for (uint64_t i = 0; i < ntasks; ++i) ord[i] = (uint32_t)i;
-  if (c->cfg.order == 1) {
-    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
-      return tasks[a].n * tasks[a].k * elem_size((int)(tasks[a].spec / 24)) >
-             tasks[b].n * tasks[b].k * elem_size((int)(tasks[b].spec / 24));
-    });
+  auto bytes_of = [&](uint32_t i) { return tasks[i].n * tasks[i].k * (uint64_t)elem_size((int)(tasks[i].spec / 24)); };
+  if (c->cfg.order == 1)
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return bytes_of(a) > bytes_of(b); });
+  else if (c->cfg.order == 2)
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return bytes_of(a) < bytes_of(b); });
+  uint64_t *hdr = reinterpret_cast<uint64_t *>(c->h_tab);
+  uint64_t *pre = reinterpret_cast<uint64_t *>(c->h_tab + prefix_off());
+  TaskD *ht = reinterpret_cast<TaskD *>(c->h_tab + tasks_off(c->cap_tasks));
+  uint64_t ntiles = 0;
+  for (uint64_t i = 0; i < ntasks; ++i) {
+    pre[i] = ntiles;
+    ht[i] = tasks[ord[i]];
+    ntiles += ht[i].ntiles;
   }
-  uint64_t w = 0;
-  auto put = [&](uint32_t t, uint64_t j) {
-    TileD &d = hl[w++];
-    d.task = t;
-    d.v0 = j * tv;
-    d.v1 = std::min<uint64_t>((j + 1) * tv, tasks[t].nvec);
-    if (d.v0 > d.v1) d.v0 = d.v1;
-    d.last = (j + 1 == tasks[t].ntiles) ? 1u : 0u;
-  };
-  if (c->cfg.order == 2) {
-    uint64_t maxt = 0;
-    for (auto &t : tasks) maxt = std::max<uint64_t>(maxt, t.ntiles);
-    for (uint64_t j = 0; j < maxt; ++j)
-      for (uint32_t t : ord)
-        if (j < tasks[t].ntiles) put(t, j);
-  } else {
-    for (uint32_t t : ord)
-      for (uint64_t j = 0; j < tasks[t].ntiles; ++j) put(t, j);
-  }
-  const size_t bytes = 256 + sizeof(TaskD) * c->cap_tasks + sizeof(TileD) * ntiles;
-  HIPCHK(hipMemcpyAsync(c->d_tab, c->h_tab, bytes, hipMemcpyHostToDevice, s));
+  pre[ntasks] = ntiles;
+  if (ntiles > 0xffffffffull) return fail(FTV_E_INVALID, "batch has too many tiles");
+  hdr[0] = ntiles;
+  hdr[1] = ntasks;
+  HIPCHK(hipMemcpyAsync(c->d_tab, c->h_tab, prefix_off() + 8 * (ntasks + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->d_tab + tasks_off(c->cap_tasks), ht, sizeof(TaskD) * ntasks,
+                        hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(c->staged, s));
   c->staged_pending = true;
   *ntiles_out = ntiles;

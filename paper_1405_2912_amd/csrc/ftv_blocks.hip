@@ -82,11 +82,32 @@ __device__ __forceinline__ uint64_t leaf_hash(const u32x4 (&v)[4]) {
   return h;
 }
 
-// Combine the leaves of one wave (64 consecutive leaves, one per lane):
-// afterwards lane 0 holds the root of the wave's subtree.
-__device__ __forceinline__ uint64_t wave_tree(uint64_t h) {
+// Root of the lane's LPT consecutive leaves (the lowest levels of the tree,
+// combined in registers).  v holds the lane's 4*LPT 16-byte chunks in order.
+template <int LPT>
+__device__ __forceinline__ uint64_t lane_subtree(const u32x4 (&v)[4 * LPT]) {
+  uint64_t h[LPT];
 #pragma unroll
-  for (int lvl = 0; lvl < 6; ++lvl) {
+  for (int j = 0; j < LPT; ++j) {
+    h[j] = kFnvBasis;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      h[j] = fnv_step(h[j], (uint64_t)v[4 * j + c].x | ((uint64_t)v[4 * j + c].y << 32));
+      h[j] = fnv_step(h[j], (uint64_t)v[4 * j + c].z | ((uint64_t)v[4 * j + c].w << 32));
+    }
+  }
+#pragma unroll
+  for (int w = LPT; w > 1; w >>= 1)
+#pragma unroll
+    for (int j = 0; j < w / 2; ++j) h[j] = fnv_node(h[2 * j], h[2 * j + 1]);
+  return h[0];
+}
+
+// Combine `levels` further levels across lanes (consecutive subtrees in
+// consecutive lanes): afterwards lane 0 of each group of 2^levels lanes holds
+// the group's root.
+__device__ __forceinline__ uint64_t lane_tree(uint64_t h, int levels) {
+  for (int lvl = 0; lvl < levels; ++lvl) {
     const uint64_t other = __shfl_xor(h, 1 << lvl, 64);
     h = fnv_node(h, other);  // meaningful on lanes whose bit `lvl` is clear
   }
@@ -100,17 +121,44 @@ __device__ __forceinline__ uint64_t lds_tree(uint64_t *sh, uint32_t nw) {
   return sh[0];
 }
 
-__global__ __launch_bounds__(1024) void k_fingerprint(const void *buf, uint64_t nbytes,
-                                                      uint64_t block_bytes, uint64_t *fp_out) {
+// The lane's LPT leaves at byte offset `off`: whole (no bounds tests) or with
+// zero padding past the end of the buffer.
+template <int LPT>
+__device__ __forceinline__ void load_leaves(const void *base, uint64_t off, uint64_t nbytes, bool whole,
+                                            u32x4 (&v)[4 * LPT]) {
+  const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + off;
+  if (whole) {
+#pragma unroll
+    for (int c = 0; c < 4 * LPT; ++c) v[c] = ld16(p, (uint64_t)c);
+  } else {
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      u32x4 w[4];
+      load_leaf(base, off + 64ull * j, nbytes, w);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[4 * j + c] = w[c];
+    }
+  }
+}
+
+__device__ __forceinline__ int ilog2(uint32_t x) { return 31 - __clz(x); }
+
+// One workgroup per block, LPT leaves per lane; levels: LPT in registers,
+// up to six across the lanes of a wave, the rest through LDS.
+template <int LPT, bool WHOLE>
+__global__ __launch_bounds__(LPT == 4 ? 256 : (LPT == 2 ? 64 : 1024)) void k_fingerprint(
+    const void *buf, uint64_t nbytes, uint64_t block_bytes, uint64_t *fp_out, uint64_t blk0) {
   __shared__ uint64_t sh[16];
-  const uint64_t blk = blockIdx.x;
-  const uint64_t off = blk * block_bytes + (uint64_t)threadIdx.x * 64;
-  u32x4 v[4];
-  load_leaf(buf, off, nbytes, v);
-  const uint64_t h = wave_tree(leaf_hash(v));
+  const uint64_t blk = blk0 + blockIdx.x;
+  const uint64_t off = blk * block_bytes + (uint64_t)threadIdx.x * (64ull * LPT);
+  u32x4 v[4 * LPT];
+  load_leaves<LPT>(buf, off, nbytes, WHOLE, v);
+  const uint32_t nth = blockDim.x;
+  const int wl = nth >= 64 ? 6 : ilog2(nth);
+  const uint64_t h = lane_tree(lane_subtree<LPT>(v), wl);
   if ((threadIdx.x & 63u) == 0) sh[threadIdx.x >> 6] = h;
   __syncthreads();
-  if (threadIdx.x == 0) fp_out[blk] = lds_tree(sh, blockDim.x >> 6);
+  if (threadIdx.x == 0) fp_out[blk] = lds_tree(sh, (nth + 63) >> 6);
 }
 
 // ---- block vote ------------------------------------------------------------
@@ -118,35 +166,36 @@ __global__ __launch_bounds__(1024) void k_fingerprint(const void *buf, uint64_t 
 // [2] unresolved elements, [3..3+K) replica blocks.
 constexpr int kBlkAcc = 3 + FTV_MAX_K;
 
-// Store a 64-byte piece at byte offset `off` of the consensus (bytes past the
-// end are not written) and zero the mask bytes of its elements.
-__device__ __forceinline__ void put_piece(const BlockVoteD &b, uint64_t off, const u32x4 (&v)[4],
-                                          bool mask_too) {
-  uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons);
-  if (off + 64 <= b.nbytes) {
+// Store the lane's piece (LPT x 64 bytes at byte offset `off`) of the
+// consensus -- bytes past the end are not written -- and, optionally, zero the
+// mask bytes of its elements.
+template <int LPT>
+__device__ __forceinline__ void put_piece(const BlockVoteD &b, uint64_t off, const u32x4 (&v)[4 * LPT],
+                                          bool whole, bool mask_too) {
+  uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons) + off;
+  const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
+  if (whole) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) st16(cb + off, (uint64_t)c, v[c], true);
-  } else {
-    // the buffer ends inside this piece (its size is a multiple of 4 bytes)
-    uint32_t *dst = reinterpret_cast<uint32_t *>(cb + off);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (off + 16ull * c + 0 < b.nbytes) dst[4 * c + 0] = v[c].x;
-      if (off + 16ull * c + 4 < b.nbytes) dst[4 * c + 1] = v[c].y;
-      if (off + 16ull * c + 8 < b.nbytes) dst[4 * c + 2] = v[c].z;
-      if (off + 16ull * c + 12 < b.nbytes) dst[4 * c + 3] = v[c].w;
+    for (int c = 0; c < 4 * LPT; ++c) st16(cb, (uint64_t)c, v[c], true);
+    if (mask_too && b.mask) {
+      uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + off / es);
+      for (uint64_t q = 0; q < (64ull * LPT / es) / 4; ++q) st_nt(mw + q, 0u, true);
     }
+    return;
+  }
+  // the buffer ends inside this piece (its size is a multiple of 4 bytes)
+  uint32_t *dst = reinterpret_cast<uint32_t *>(cb);
+#pragma unroll
+  for (int c = 0; c < 4 * LPT; ++c) {
+    if (off + 16ull * c + 0 < b.nbytes) dst[4 * c + 0] = v[c].x;
+    if (off + 16ull * c + 4 < b.nbytes) dst[4 * c + 1] = v[c].y;
+    if (off + 16ull * c + 8 < b.nbytes) dst[4 * c + 2] = v[c].z;
+    if (off + 16ull * c + 12 < b.nbytes) dst[4 * c + 3] = v[c].w;
   }
   if (mask_too && b.mask) {
-    const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
     const uint64_t e0 = off / es;
-    const uint64_t e1 = (off + 64 < b.nbytes ? off + 64 : b.nbytes) / es;
-    if (e1 - e0 == 64 / es) {  // whole piece: 16 (4-byte) or 8 (8-byte) mask bytes
-      uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + e0);
-      for (uint64_t q = 0; q < (64 / es) / 4; ++q) st_nt(mw + q, 0u, true);
-    } else {
-      for (uint64_t e = e0; e < e1; ++e) b.mask[e] = 0;
-    }
+    const uint64_t end = off + 64ull * LPT < b.nbytes ? off + 64ull * LPT : b.nbytes;
+    for (uint64_t e = e0; e < end / es; ++e) b.mask[e] = 0;
   }
 }
 
@@ -162,49 +211,41 @@ __device__ __forceinline__ const void *rep_ptr(const BlockVoteD &b, int r) {
 
 // Pass 1: fingerprints of the block in all k replicas, their vote, the block
 // map, and the restore.  Replica 0's piece is written to the consensus while
-// it is hashed (one leaf per lane is live at a time); only a block whose
-// majority fingerprint differs from replica 0's is copied again, from the
-// source replica.  Blocks without a majority are left to pass 2, which
-// rewrites their consensus and mask.
-template <int K>
-__global__ __launch_bounds__(1024, 8) void k_vote_blocks(BlockVoteD b) {
-  __shared__ uint64_t sh[K][16];
-  const uint64_t blk = blockIdx.x;
-  const uint64_t off = blk * b.block_bytes + (uint64_t)threadIdx.x * 64;
-  const uint32_t nw = blockDim.x >> 6;
-  // one replica at a time (not unrolled): a single leaf per lane is live, which
-  // keeps two 1024-lane workgroups resident per CU to overlap their phases.
-  // Whole blocks (all but possibly the last) take a path without bounds tests.
-  if ((blk + 1) * b.block_bytes <= b.nbytes) {
-    const uint8_t *cb = reinterpret_cast<const uint8_t *>(b.cons);
+// it is hashed (one replica's leaves per lane are live at a time); only a
+// block whose majority fingerprint differs from replica 0's is copied again,
+// from the source replica.  Blocks without a majority are left to pass 2,
+// which rewrites their consensus and mask.
+// Hash the lane's piece of every replica (one replica at a time, not
+// unrolled, so that only one replica's leaves are live) and stream replica
+// 0's piece into the consensus.  WHOLE: the block lies inside the buffer.
+template <int K, int LPT, bool WHOLE>
+__device__ __forceinline__ void hash_replicas(const BlockVoteD &b, uint64_t off, int wl,
+                                              uint64_t (*sh)[16]) {
+  const bool mine = off < b.nbytes;
 #pragma unroll 1
-    for (int r = 0; r < K; ++r) {
-      const uint8_t *p = reinterpret_cast<const uint8_t *>(rep_ptr<K>(b, r)) + off;
-      u32x4 v[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = ld16(p, (uint64_t)c);
-      if (r == 0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) st16((void *)(cb + off), (uint64_t)c, v[c], true);
-        if (b.mask) {
-          const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
-          uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + off / es);
-          for (uint64_t q = 0; q < (64 / es) / 4; ++q) st_nt(mw + q, 0u, true);
-        }
-      }
-      const uint64_t h = wave_tree(leaf_hash(v));
-      if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
-    }
-  } else {
-#pragma unroll 1
-    for (int r = 0; r < K; ++r) {
-      u32x4 v[4];
-      load_leaf(rep_ptr<K>(b, r), off, b.nbytes, v);
-      if (r == 0 && off < b.nbytes) put_piece(b, off, v, true);
-      const uint64_t h = wave_tree(leaf_hash(v));
-      if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
-    }
+  for (int r = 0; r < K; ++r) {
+    u32x4 v[4 * LPT];
+    load_leaves<LPT>(rep_ptr<K>(b, r), off, b.nbytes, WHOLE, v);
+    if (r == 0 && mine) put_piece<LPT>(b, off, v, WHOLE, true);
+    const uint64_t h = lane_tree(lane_subtree<LPT>(v), wl);
+    if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
   }
+}
+
+// WHOLE: every block of the launch lies inside the buffer (all but a partial
+// last block, which gets a launch of its own with WHOLE = false, LPT = 1).
+template <int K, int LPT, bool WHOLE>
+__global__ __launch_bounds__(LPT == 4 ? 256 : (LPT == 2 ? 64 : 1024)) void k_vote_blocks(BlockVoteD b,
+                                                                                       uint64_t blk0) {
+  __shared__ uint64_t sh[K][16];
+  const uint64_t blk = blk0 + blockIdx.x;
+  const uint64_t off = blk * b.block_bytes + (uint64_t)threadIdx.x * (64ull * LPT);
+  const uint32_t nth = blockDim.x;
+  const uint32_t nw = (nth + 63) >> 6;
+  const int wl = nth >= 64 ? 6 : ilog2(nth);
+  constexpr bool whole = WHOLE;
+  const bool mine = off < b.nbytes;
+  hash_replicas<K, LPT, WHOLE>(b, off, wl, sh);
   __syncthreads();
   if (threadIdx.x < (uint32_t)K) {
     const uint32_t r = threadIdx.x;
@@ -233,10 +274,10 @@ __global__ __launch_bounds__(1024, 8) void k_vote_blocks(BlockVoteD b) {
   for (int r = 0; r < K; ++r) bm |= (uint32_t)(fp_r[r] != fp_r[src]) << r;
   const bool majority = 2 * M > K;
   if (!majority) bm |= 0x80u;
-  if (majority && (bm & 1u) && off < b.nbytes) {  // replica 0 is not the majority: recopy
-    u32x4 v[4];
-    load_leaf(rep_ptr<K>(b, src), off, b.nbytes, v);
-    put_piece(b, off, v, false);
+  if (majority && (bm & 1u) && mine) {  // replica 0 is not the majority: recopy
+    u32x4 v[4 * LPT];
+    load_leaves<LPT>(rep_ptr<K>(b, src), off, b.nbytes, whole, v);
+    put_piece<LPT>(b, off, v, whole, false);
   }
   if (threadIdx.x == 0) {
     b.blockmap[blk] = (uint8_t)bm;
@@ -344,11 +385,35 @@ hipError_t launch_fallback(const BlockVoteD &b, int num_cus, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Leaves per lane: 4 when the block has at least 256 leaves, so that each
+// lane combines two tree levels in registers; smaller blocks keep one wave.
+inline int leaves_per_lane(uint64_t block_bytes) {
+  const uint64_t leaves = block_bytes / 64;
+  return leaves >= 256 ? 4 : (leaves >= 128 ? 2 : 1);
+}
+
+template <int K, int LPT>
+hipError_t launch_blocks_kl(const BlockVoteD &b, hipStream_t s) {
+  const uint64_t nwhole = b.nbytes / b.block_bytes;
+  if (nwhole) {
+    const dim3 grid((uint32_t)nwhole), block((uint32_t)(b.block_bytes / 64 / LPT));
+    hipLaunchKernelGGL((k_vote_blocks<K, LPT, true>), grid, block, 0, s, b, (uint64_t)0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (nwhole < b.nblocks) {  // the partial last block
+    hipLaunchKernelGGL((k_vote_blocks<K, 1, false>), dim3(1), dim3((uint32_t)(b.block_bytes / 64)), 0, s,
+                       b, nwhole);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
 template <int K>
 hipError_t launch_blocks_k(const BlockVoteD &b, int num_cus, hipStream_t s) {
-  const dim3 grid((uint32_t)b.nblocks), block((uint32_t)(b.block_bytes / 64));
-  hipLaunchKernelGGL((k_vote_blocks<K>), grid, block, 0, s, b);
-  hipError_t e = hipGetLastError();
+  const int lpt = leaves_per_lane(b.block_bytes);
+  hipError_t e = lpt == 4 ? launch_blocks_kl<K, 4>(b, s)
+                          : (lpt == 2 ? launch_blocks_kl<K, 2>(b, s) : launch_blocks_kl<K, 1>(b, s));
   if (e != hipSuccess) return e;
   switch (b.dtype * 3 + b.tolkind) {
     case FTV_F32 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_F32, FTV_TOL_EXACT, K>(b, num_cus, s);
@@ -369,8 +434,20 @@ hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_b
                               uint64_t *fp_out, hipStream_t s) {
   const uint64_t nblocks = (nbytes + block_bytes - 1) / block_bytes;
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fingerprint, dim3((uint32_t)nblocks), dim3((uint32_t)(block_bytes / 64)), 0, s,
-                     buf, nbytes, block_bytes, fp_out);
+  const int lpt = leaves_per_lane(block_bytes);
+  const uint64_t nwhole = nbytes / block_bytes;
+  if (nwhole) {
+    const dim3 grid((uint32_t)nwhole), block((uint32_t)(block_bytes / 64 / lpt));
+    const uint64_t z = 0;
+    if (lpt == 4) hipLaunchKernelGGL((k_fingerprint<4, true>), grid, block, 0, s, buf, nbytes, block_bytes, fp_out, z);
+    else if (lpt == 2) hipLaunchKernelGGL((k_fingerprint<2, true>), grid, block, 0, s, buf, nbytes, block_bytes, fp_out, z);
+    else hipLaunchKernelGGL((k_fingerprint<1, true>), grid, block, 0, s, buf, nbytes, block_bytes, fp_out, z);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (nwhole < nblocks)  // the partial last block
+    hipLaunchKernelGGL((k_fingerprint<1, false>), dim3(1), dim3((uint32_t)(block_bytes / 64)), 0, s, buf, nbytes,
+                       block_bytes, fp_out, nwhole);
   return hipGetLastError();
 }
 

@@ -60,16 +60,22 @@ int elem_size(int dtype);
 // ---- launchers (ftv_vote.hip) -------------------------------------------
 hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
 
+// A persistent launch over a queue of tiles.  Two ways to name the tiles:
+//  * prefix mode (batched calls): prefix[t] = first tile of task t (ntasks+1
+//    entries); tile j of task t covers vectors [j*tile_vecs, (j+1)*tile_vecs);
+//  * table mode (server iterations, prefix == nullptr): explicit TileD entries.
 struct BatchLaunch {
-  const TaskD *tasks;     // device
-  const TileD *tiles;     // device
+  const TaskD *tasks;          // device
+  const TileD *tiles;          // device, table mode
+  const uint64_t *prefix;      // device, prefix mode
   const uint64_t *ntiles_dev;  // device: [0] = tiles, [1] = tasks
-  uint64_t *acc;          // device [ntasks][kNumCounters]
-  uint32_t *task_done;    // device [ntasks]
-  uint32_t *queue_head;   // device
+  uint64_t *acc;               // device [ntasks][kNumCounters]
+  uint32_t *task_done;         // device [ntasks]
+  uint32_t *queue_head;        // device
   uint32_t block;
   uint32_t grid;
   uint32_t nt_stores;
+  uint32_t tile_vecs;          // prefix mode
 };
 hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s);

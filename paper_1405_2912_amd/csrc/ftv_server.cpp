@@ -281,6 +281,8 @@ int launch_iteration(ftv_server *s, Iter &it) {
     BatchLaunch b;
     b.tasks = s->d_tasks;
     b.tiles = reinterpret_cast<const TileD *>(it.d_buf + 256 + sizeof(uint32_t) * s->cfg.max_slots);
+    b.prefix = nullptr;  // table mode: the iteration lists its tiles
+    b.tile_vecs = kTileVecs;
     b.ntiles_dev = d_hdr;
     b.acc = s->d_acc;
     b.task_done = s->d_done;

@@ -120,14 +120,39 @@ __global__ __launch_bounds__(512) void k_vote_batch(BatchLaunch b) {
   __shared__ uint64_t sh[16 * kNumCounters];
   __shared__ uint64_t s_tot[kNumCounters];
   __shared__ uint32_t s_tile, s_last;
+  __shared__ TileD s_tl;
   const uint64_t ntiles = b.ntiles_dev[0];
+  const uint64_t ntasks = b.ntiles_dev[1];
   for (;;) {
-    if (threadIdx.x == 0)
-      s_tile = __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      const uint32_t q = __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_tile = q;
+      if (q < ntiles) {
+        if (b.prefix) {
+          // the task whose tile range holds q: last t with prefix[t] <= q
+          uint64_t lo = 0, hi = ntasks;
+          while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (b.prefix[mid] <= q) lo = mid;
+            else hi = mid;
+          }
+          const uint64_t j = q - b.prefix[lo];
+          const uint64_t nvec = b.tasks[lo].nvec;
+          TileD tl;
+          tl.task = (uint32_t)lo;
+          tl.v0 = j * b.tile_vecs < nvec ? j * b.tile_vecs : nvec;
+          tl.v1 = tl.v0 + b.tile_vecs < nvec ? tl.v0 + b.tile_vecs : nvec;
+          tl.last = (q + 1 == b.prefix[lo + 1]) ? 1u : 0u;
+          s_tl = tl;
+        } else {
+          s_tl = b.tiles[q];
+        }
+      }
+    }
     __syncthreads();
     const uint32_t ti = s_tile;
     if (ti >= ntiles) break;
-    const TileD tile = b.tiles[ti];
+    const TileD tile = s_tl;
     const TaskD &t = b.tasks[tile.task];  // read in place: a copy would go to scratch
     switch (t.spec) {
       FTV_CASES_K(FTV_F32, FTV_TOL_EXACT)

@@ -151,3 +151,25 @@ def test_batch_alignment_is_checked(gpu, ctx):
     with pytest.raises(gpu.FtvError) as e:
         gpu.vote_batch(ctx, [d])
     assert e.value.code == gpu.E_ALIGN
+
+
+def test_tune_cache_roundtrip(gpu, ctx, tmp_path, monkeypatch):
+    """The autotuner stores its choice as JSON and reuses it on a cache hit;
+    the cached schedule gives the same results."""
+    import json
+    rng = np.random.default_rng(44)
+    tasks, descs, stats = make_batch(gpu, rng, 40, 50000, ks=(2, 3, 5))
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("FTV_TUNE_CACHE", str(path))
+    best = gpu.tune_batch(ctx, descs, iters=1)
+    ref = outputs(gpu, tasks, stats)
+    check_oracle(tasks, ref)
+    doc = json.loads(path.read_text())
+    assert len(doc) == 1
+    (key, val), = doc.items()
+    assert val == [best.tile_vecs, best.block, best.grid_mult, best.order, best.nt_stores]
+    # a different schedule in the cache file is picked up as is
+    path.write_text(json.dumps({key: [1024, 512, 2, 2, 0]}))
+    again = gpu.tune_batch(ctx, descs, iters=1)
+    assert (again.tile_vecs, again.block, again.grid_mult, again.order, again.nt_stores) == (1024, 512, 2, 2, 0)
+    assert same(outputs(gpu, tasks, stats), ref)
