@@ -106,14 +106,12 @@ struct ftv_ctx {
   std::string name;
   // per-task launch workspace: count accumulators (zero between launches)
   uint64_t *partials = nullptr;
-  uint32_t *ticket = nullptr;
   // batched launch
   ftv_batch_cfg cfg{};
   uint64_t cap_tasks = 0;
   char *d_tab = nullptr;   // [hdr 256 B][prefix u64 x (cap_tasks+1)][TaskD x cap_tasks]
   char *h_tab = nullptr;   // pinned staging of the same layout
   uint64_t *d_acc = nullptr;
-  uint32_t *d_done = nullptr;
   uint32_t *d_queue = nullptr;
   hipEvent_t staged{};
   bool staged_pending = false;
@@ -125,7 +123,6 @@ struct ftv_ctx {
   ftv_batch_cfg g_cfg{};
   // block vote workspace
   uint64_t *blk_acc = nullptr;
-  uint32_t *blk_ticket = nullptr;
 };
 
 namespace {
@@ -153,11 +150,9 @@ void free_batch(ftv_ctx *c) {
   if (c->d_tab) (void)hipFree(c->d_tab);
   if (c->h_tab) (void)hipHostFree(c->h_tab);
   if (c->d_acc) (void)hipFree(c->d_acc);
-  if (c->d_done) (void)hipFree(c->d_done);
   c->d_tab = nullptr;
   c->h_tab = nullptr;
   c->d_acc = nullptr;
-  c->d_done = nullptr;
   c->cap_tasks = 0;
 }
 
@@ -170,8 +165,7 @@ int ensure_capacity(ftv_ctx *c, uint64_t tasks, hipStream_t s) {
   const uint64_t nt = std::max<uint64_t>(tasks + tasks / 2, 1024);
   const size_t tb = tab_bytes(nt);
   if (hipMalloc(&c->d_tab, tb) != hipSuccess || hipHostMalloc(&c->h_tab, tb) != hipSuccess ||
-      hipMalloc(&c->d_acc, sizeof(uint64_t) * kNumCounters * nt) != hipSuccess ||
-      hipMalloc(&c->d_done, sizeof(uint32_t) * nt) != hipSuccess) {
+      hipMalloc(&c->d_acc, sizeof(uint64_t) * kNumCounters * nt) != hipSuccess) {
     (void)hipGetLastError();
     free_batch(c);
     return fail(FTV_E_NOMEM, "cannot allocate the batch tables");
@@ -187,7 +181,6 @@ BatchLaunch make_launch(ftv_ctx *c, uint32_t grid) {
   b.prefix = reinterpret_cast<const uint64_t *>(c->d_tab + prefix_off());
   b.ntiles_dev = reinterpret_cast<const uint64_t *>(c->d_tab);
   b.acc = c->d_acc;
-  b.task_done = c->d_done;
   b.queue_head = c->d_queue;
   b.block = c->cfg.block;
   b.grid = grid;
@@ -196,7 +189,7 @@ BatchLaunch make_launch(ftv_ctx *c, uint32_t grid) {
   return b;
 }
 
-// Capture zero + persistent kernels once per (capacity, grid, cfg); the
+// Capture zero + persistent + finalize kernels once per (capacity, grid, cfg); the
 // kernels read the task and tile counts from the table header, so a new batch
 // only needs a new table upload.
 int ensure_graph(ftv_ctx *c, uint32_t grid) {
@@ -210,10 +203,12 @@ int ensure_graph(ftv_ctx *c, uint32_t grid) {
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t e1 = launch_batch_zero(b, c->cap_stream);
   hipError_t e2 = launch_batch_vote(b, c->cap_stream);
+  hipError_t e2f = launch_batch_finalize(b, c->cap_stream);
   hipGraph_t g{};
   hipError_t e3 = hipStreamEndCapture(c->cap_stream, &g);
   if (e1 != hipSuccess) return hip_fail(e1, "capture zero kernel");
   if (e2 != hipSuccess) return hip_fail(e2, "capture batch kernel");
+  if (e2f != hipSuccess) return hip_fail(e2f, "capture finalize kernel");
   if (e3 != hipSuccess) return hip_fail(e3, "hipStreamEndCapture");
   hipError_t e4 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
   if (e4 != hipSuccess) {
@@ -383,9 +378,7 @@ int ftv_ctx_create(int device, ftv_ctx **out) {
   c->cfg = kDefaultCfg;
   bool ok = hipMalloc(&c->partials, sizeof(uint64_t) * kNumCounters) == hipSuccess &&
             hipMemset(c->partials, 0, sizeof(uint64_t) * kNumCounters) == hipSuccess &&
-            hipMalloc(&c->ticket, 256) == hipSuccess && hipMalloc(&c->d_queue, 256) == hipSuccess &&
-            hipMalloc(&c->blk_acc, 256) == hipSuccess && hipMalloc(&c->blk_ticket, 256) == hipSuccess &&
-            hipMemset(c->ticket, 0, 256) == hipSuccess && hipMemset(c->blk_ticket, 0, 256) == hipSuccess &&
+            hipMalloc(&c->d_queue, 256) == hipSuccess && hipMalloc(&c->blk_acc, 256) == hipSuccess &&
             hipMemset(c->blk_acc, 0, 256) == hipSuccess &&
             hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) == hipSuccess &&
             hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess &&
@@ -405,10 +398,8 @@ int ftv_ctx_destroy(ftv_ctx *c) {
   (void)hipDeviceSynchronize();
   free_batch(c);
   if (c->partials) (void)hipFree(c->partials);
-  if (c->ticket) (void)hipFree(c->ticket);
   if (c->d_queue) (void)hipFree(c->d_queue);
   if (c->blk_acc) (void)hipFree(c->blk_acc);
-  if (c->blk_ticket) (void)hipFree(c->blk_ticket);
   if (c->staged) (void)hipEventDestroy(c->staged);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
@@ -420,7 +411,7 @@ int ftv_vote(ftv_ctx *c, const ftv_vote_desc *desc, void *stream) {
   TaskD t;
   int rc = make_task(desc, false, &t);
   if (rc) return rc;
-  VoteWs ws{c->partials, c->ticket};
+  VoteWs ws{c->partials};
   hipError_t e = launch_vote_task(t, ws, c->num_cus, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
   return FTV_OK;
@@ -591,7 +582,6 @@ int ftv_vote_blocks(ftv_ctx *c, const void *const *replicas, uint32_t k, int32_t
   b.mask = mask;
   b.bstats = bstats;
   b.acc = c->blk_acc;
-  b.ticket = c->blk_ticket;
   hipError_t e = launch_vote_blocks(b, c->num_cus, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "block vote kernel launch");
   return FTV_OK;

@@ -4,17 +4,35 @@
 // is read as little-endian 64-bit words, zero-padded past the end of the
 // buffer; a leaf is 64-bit FNV-1a over 8 consecutive words (64 B) and leaves
 // are combined pairwise, level by level, a node being FNV-1a over the two words
-// (left, right).  One workgroup hashes one block with one leaf per thread:
-// the first six levels of the tree are combined across the lanes of a wave,
-// the remaining ones (up to four, for 16 waves) through LDS.
+// (left, right).
+//
+// Whole blocks: one workgroup of T = min(256, BB/64) threads per block walks
+// it in sub-chunks of 64*T bytes (one leaf per thread).  The sub-chunk is
+// read with fully coalesced 16-byte loads (chunk c*T + t to thread t, so each
+// load instruction of a wave covers 1 KiB of consecutive bytes), transposed
+// through LDS (double-buffered, XOR-swizzled so that neither the writes nor
+// the leaf-major reads conflict on banks) so that thread t then holds leaf t.
+// The first six tree levels are combined across the lanes of a wave, the next
+// (up to two) over the wave roots in LDS, the last (up to two) over the
+// sub-chunk roots.  The loads of the next sub-chunk are in flight while the
+// current one is hashed.  Reading each lane's own 64-byte leaf directly from
+// HBM instead (lanes 64 bytes apart in every load) measured 1.6x slower.
 //
 // Block vote: the same workgroup hashes the block in all k replicas, votes
 // the k fingerprints by exact equality and restores the consensus from the
 // lowest-indexed replica holding a strict-majority fingerprint.  Replica 0's
 // data is streamed into the consensus while it is hashed, so in the common
 // case (replica 0 agrees with the majority) the restore costs one write pass
-// and no extra read.  Blocks without a majority fall back to the element vote
-// over their elements in a second, small kernel.
+// and no extra read.  A second kernel scans the block map: it counts the
+// map's statistics per workgroup and runs the element vote over every block
+// without a majority; a one-workgroup finalize kernel writes the stats.  No
+// kernel of the three waits on another's workgroups: kernel boundaries on
+// the stream order them.
+//
+// A partial last block (the buffer ends inside it) is handled by one
+// workgroup of BB/64 threads reading its leaves directly, with zero padding.
+#include <string.h>
+
 #include "ftv_internal.hpp"
 #include "ftv_vote_dev.hpp"
 
@@ -25,13 +43,14 @@ using namespace dev;
 
 constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
 
-// (h ^ w) * 0x100000001b3 mod 2^64, with the prime split as 2^40 + 0x1b3.
+// (h ^ w) * 0x100000001b3 mod 2^64.  With x = hi:lo and the prime split as
+// 2^40 + 0x1b3: x * P = lo * 0x1b3 + ((hi * 0x1b3 + (lo << 8)) mod 2^32) * 2^32
+// (mod 2^64) -- one 32x32->64 multiply-add and one 32-bit multiply.
 __device__ __forceinline__ uint64_t fnv_step(uint64_t h, uint64_t w) {
   const uint64_t x = h ^ w;
   const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-  const uint64_t p = (uint64_t)lo * 0x1b3u;
-  const uint32_t phi = (uint32_t)(p >> 32) + hi * 0x1b3u + (lo << 8);
-  return ((uint64_t)phi << 32) | (uint32_t)p;
+  const uint32_t upper = hi * 0x1b3u + (lo << 8);
+  return (uint64_t)lo * 0x1b3u + ((uint64_t)upper << 32);
 }
 
 __device__ __forceinline__ uint64_t fnv_node(uint64_t l, uint64_t r) {
@@ -82,27 +101,6 @@ __device__ __forceinline__ uint64_t leaf_hash(const u32x4 (&v)[4]) {
   return h;
 }
 
-// Root of the lane's LPT consecutive leaves (the lowest levels of the tree,
-// combined in registers).  v holds the lane's 4*LPT 16-byte chunks in order.
-template <int LPT>
-__device__ __forceinline__ uint64_t lane_subtree(const u32x4 (&v)[4 * LPT]) {
-  uint64_t h[LPT];
-#pragma unroll
-  for (int j = 0; j < LPT; ++j) {
-    h[j] = kFnvBasis;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      h[j] = fnv_step(h[j], (uint64_t)v[4 * j + c].x | ((uint64_t)v[4 * j + c].y << 32));
-      h[j] = fnv_step(h[j], (uint64_t)v[4 * j + c].z | ((uint64_t)v[4 * j + c].w << 32));
-    }
-  }
-#pragma unroll
-  for (int w = LPT; w > 1; w >>= 1)
-#pragma unroll
-    for (int j = 0; j < w / 2; ++j) h[j] = fnv_node(h[2 * j], h[2 * j + 1]);
-  return h[0];
-}
-
 // Combine `levels` further levels across lanes (consecutive subtrees in
 // consecutive lanes): afterwards lane 0 of each group of 2^levels lanes holds
 // the group's root.
@@ -114,90 +112,14 @@ __device__ __forceinline__ uint64_t lane_tree(uint64_t h, int levels) {
   return h;
 }
 
-// Reduce `nw` wave roots in LDS (pairwise, in order) to the block root.
+// Reduce `nw` roots in LDS (pairwise, in order) to one.
 __device__ __forceinline__ uint64_t lds_tree(uint64_t *sh, uint32_t nw) {
   for (uint32_t len = nw; len > 1; len >>= 1)
     for (uint32_t j = 0; j < len / 2; ++j) sh[j] = fnv_node(sh[2 * j], sh[2 * j + 1]);
   return sh[0];
 }
 
-// The lane's LPT leaves at byte offset `off`: whole (no bounds tests) or with
-// zero padding past the end of the buffer.
-template <int LPT>
-__device__ __forceinline__ void load_leaves(const void *base, uint64_t off, uint64_t nbytes, bool whole,
-                                            u32x4 (&v)[4 * LPT]) {
-  const uint8_t *p = reinterpret_cast<const uint8_t *>(base) + off;
-  if (whole) {
-#pragma unroll
-    for (int c = 0; c < 4 * LPT; ++c) v[c] = ld16(p, (uint64_t)c);
-  } else {
-#pragma unroll
-    for (int j = 0; j < LPT; ++j) {
-      u32x4 w[4];
-      load_leaf(base, off + 64ull * j, nbytes, w);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[4 * j + c] = w[c];
-    }
-  }
-}
-
 __device__ __forceinline__ int ilog2(uint32_t x) { return 31 - __clz(x); }
-
-// One workgroup per block, LPT leaves per lane; levels: LPT in registers,
-// up to six across the lanes of a wave, the rest through LDS.
-template <int LPT, bool WHOLE>
-__global__ __launch_bounds__(LPT == 4 ? 256 : (LPT == 2 ? 64 : 1024)) void k_fingerprint(
-    const void *buf, uint64_t nbytes, uint64_t block_bytes, uint64_t *fp_out, uint64_t blk0) {
-  __shared__ uint64_t sh[16];
-  const uint64_t blk = blk0 + blockIdx.x;
-  const uint64_t off = blk * block_bytes + (uint64_t)threadIdx.x * (64ull * LPT);
-  u32x4 v[4 * LPT];
-  load_leaves<LPT>(buf, off, nbytes, WHOLE, v);
-  const uint32_t nth = blockDim.x;
-  const int wl = nth >= 64 ? 6 : ilog2(nth);
-  const uint64_t h = lane_tree(lane_subtree<LPT>(v), wl);
-  if ((threadIdx.x & 63u) == 0) sh[threadIdx.x >> 6] = h;
-  __syncthreads();
-  if (threadIdx.x == 0) fp_out[blk] = lds_tree(sh, (nth + 63) >> 6);
-}
-
-// ---- block vote ------------------------------------------------------------
-// Workspace accumulators: [0] disagree blocks, [1] fallback blocks,
-// [2] unresolved elements, [3..3+K) replica blocks.
-constexpr int kBlkAcc = 3 + FTV_MAX_K;
-
-// Store the lane's piece (LPT x 64 bytes at byte offset `off`) of the
-// consensus -- bytes past the end are not written -- and, optionally, zero the
-// mask bytes of its elements.
-template <int LPT>
-__device__ __forceinline__ void put_piece(const BlockVoteD &b, uint64_t off, const u32x4 (&v)[4 * LPT],
-                                          bool whole, bool mask_too) {
-  uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons) + off;
-  const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
-  if (whole) {
-#pragma unroll
-    for (int c = 0; c < 4 * LPT; ++c) st16(cb, (uint64_t)c, v[c], true);
-    if (mask_too && b.mask) {
-      uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + off / es);
-      for (uint64_t q = 0; q < (64ull * LPT / es) / 4; ++q) st_nt(mw + q, 0u, true);
-    }
-    return;
-  }
-  // the buffer ends inside this piece (its size is a multiple of 4 bytes)
-  uint32_t *dst = reinterpret_cast<uint32_t *>(cb);
-#pragma unroll
-  for (int c = 0; c < 4 * LPT; ++c) {
-    if (off + 16ull * c + 0 < b.nbytes) dst[4 * c + 0] = v[c].x;
-    if (off + 16ull * c + 4 < b.nbytes) dst[4 * c + 1] = v[c].y;
-    if (off + 16ull * c + 8 < b.nbytes) dst[4 * c + 2] = v[c].z;
-    if (off + 16ull * c + 12 < b.nbytes) dst[4 * c + 3] = v[c].w;
-  }
-  if (mask_too && b.mask) {
-    const uint64_t e0 = off / es;
-    const uint64_t end = off + 64ull * LPT < b.nbytes ? off + 64ull * LPT : b.nbytes;
-    for (uint64_t e = e0; e < end / es; ++e) b.mask[e] = 0;
-  }
-}
 
 // b.rep[r] for a runtime r, as a select chain: indexing the by-value kernel
 // argument with a runtime index would copy it to scratch memory.
@@ -209,61 +131,120 @@ __device__ __forceinline__ const void *rep_ptr(const BlockVoteD &b, int r) {
   return p;
 }
 
-// Pass 1: fingerprints of the block in all k replicas, their vote, the block
-// map, and the restore.  Replica 0's piece is written to the consensus while
-// it is hashed (one replica's leaves per lane are live at a time); only a
-// block whose majority fingerprint differs from replica 0's is copied again,
-// from the source replica.  Blocks without a majority are left to pass 2,
-// which rewrites their consensus and mask.
-// Hash the lane's piece of every replica (one replica at a time, not
-// unrolled, so that only one replica's leaves are live) and stream replica
-// 0's piece into the consensus.  WHOLE: the block lies inside the buffer.
-template <int K, int LPT, bool WHOLE>
-__device__ __forceinline__ void hash_replicas(const BlockVoteD &b, uint64_t off, int wl,
-                                              uint64_t (*sh)[16]) {
-  const bool mine = off < b.nbytes;
-#pragma unroll 1
-  for (int r = 0; r < K; ++r) {
-    u32x4 v[4 * LPT];
-    load_leaves<LPT>(rep_ptr<K>(b, r), off, b.nbytes, WHOLE, v);
-    if (r == 0 && mine) put_piece<LPT>(b, off, v, WHOLE, true);
-    const uint64_t h = lane_tree(lane_subtree<LPT>(v), wl);
-    if ((threadIdx.x & 63u) == 0) sh[r][threadIdx.x >> 6] = h;
-  }
+// ---- whole blocks: coalesced loads transposed through LDS -----------------
+constexpr uint32_t kMaxT = 256;         // threads per block workgroup
+constexpr uint32_t kSubChunks = 4 * kMaxT;  // 16-byte chunks per sub-chunk (max)
+
+// LDS slot of 16-byte chunk g of a sub-chunk.  Thread t writes chunks c*T + t
+// and reads chunks 4t .. 4t+3; XOR-ing bits 0-1 with bits 4-5 makes every
+// group of 16 lanes hit 16 distinct 16-byte bank groups in both patterns.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t g) { return g ^ ((g >> 4) & 3u); }
+
+// Geometry of a whole-block walk: step s = (buffer s >> lg_nsub, sub-chunk
+// s & (nsub - 1)); a sub-chunk is 64*T bytes.
+struct Walk {
+  uint64_t boff;      // byte offset of the block
+  uint32_t nth;       // T
+  uint32_t sub_bytes; // 64 * T
+  uint32_t lg_nsub;
+  uint32_t nsub;
+};
+
+template <int K>
+__device__ __forceinline__ void load_step(const BlockVoteD &b, const Walk &w, uint32_t s, u32x4 (&v)[4]) {
+  const uint32_t r = s >> w.lg_nsub, sub = s & (w.nsub - 1);
+  const uint8_t *p = reinterpret_cast<const uint8_t *>(rep_ptr<K>(b, (int)r)) + w.boff +
+                     (uint64_t)sub * w.sub_bytes + 16ull * threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = ld16(p, (uint64_t)c * w.nth);
 }
 
-// WHOLE: every block of the launch lies inside the buffer (all but a partial
-// last block, which gets a launch of its own with WHOLE = false, LPT = 1).
-template <int K, int LPT, bool WHOLE>
-__global__ __launch_bounds__(LPT == 4 ? 256 : (LPT == 2 ? 64 : 1024)) void k_vote_blocks(BlockVoteD b,
-                                                                                       uint64_t blk0) {
-  __shared__ uint64_t sh[K][16];
-  const uint64_t blk = blk0 + blockIdx.x;
-  const uint64_t off = blk * b.block_bytes + (uint64_t)threadIdx.x * (64ull * LPT);
-  const uint32_t nth = blockDim.x;
-  const uint32_t nw = (nth + 63) >> 6;
-  const int wl = nth >= 64 ? 6 : ilog2(nth);
-  constexpr bool whole = WHOLE;
-  const bool mine = off < b.nbytes;
-  hash_replicas<K, LPT, WHOLE>(b, off, wl, sh);
+// Hash step s held in v: buffer 0's chunks also go to the consensus (mask
+// bytes of their elements zeroed) when CONS.  Leaves sroot[r][sub].
+template <bool CONS>
+__device__ __forceinline__ void hash_step(const BlockVoteD &b, const Walk &w, uint32_t s, const u32x4 (&v)[4],
+                                          u32x4 *lbuf, uint64_t *sw, uint64_t (*sroot)[4]) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t r = s >> w.lg_nsub, sub = s & (w.nsub - 1);
+  const uint64_t soff = w.boff + (uint64_t)sub * w.sub_bytes;
+  if (CONS && r == 0) {
+    uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons) + soff + 16ull * t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) st16(cb, (uint64_t)c * w.nth, v[c], true);
+    if (b.mask) {
+      // 64 bytes of the sub-chunk per thread = 8 (8-byte) or 16 (4-byte) elements
+      const uint32_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4u : 8u;
+      const uint32_t per = 64u / es;
+      uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + soff / es + (uint64_t)t * per);
+      for (uint32_t q = 0; q < per / 4; ++q) st_nt(mw + q, 0u, true);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) lbuf[lds_slot((uint32_t)c * w.nth + t)] = v[c];
   __syncthreads();
-  if (threadIdx.x < (uint32_t)K) {
-    const uint32_t r = threadIdx.x;
-    const uint64_t f = lds_tree(sh[r], nw);
-    sh[r][0] = f;
-    if (b.fps) b.fps[(uint64_t)r * b.nblocks + blk] = f;
+  u32x4 leaf[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) leaf[q] = lbuf[lds_slot(4u * t + q)];
+  const uint64_t h = lane_tree(leaf_hash(leaf), 6);
+  if ((t & 63u) == 0) sw[t >> 6] = h;
+  __syncthreads();
+  if (t == 0) sroot[r][sub] = lds_tree(sw, w.nth >> 6);
+}
+
+// Sub-chunk roots of block `blk` in the first K buffers of b (K = 1:
+// fingerprints of b.rep[0]), the next step's loads in flight while one is
+// hashed.  Ends with a barrier: sroot is then complete.
+template <int K, bool CONS>
+__device__ __forceinline__ void walk_block(const BlockVoteD &b, const Walk &w, u32x4 (*lbuf)[kSubChunks],
+                                           uint64_t *sw, uint64_t (*sroot)[4]) {
+  const uint32_t nstep = (uint32_t)K << w.lg_nsub;
+  u32x4 va[4], vb[4];
+  load_step<K>(b, w, 0, va);
+  for (uint32_t s = 0; s < nstep; s += 2) {
+    if (s + 1 < nstep) load_step<K>(b, w, s + 1, vb);
+    hash_step<CONS>(b, w, s, va, lbuf[0], sw, sroot);
+    if (s + 1 >= nstep) break;
+    if (s + 2 < nstep) load_step<K>(b, w, s + 2, va);
+    hash_step<CONS>(b, w, s + 1, vb, lbuf[1], sw, sroot);
   }
   __syncthreads();
-  uint64_t fp_r[K];
-#pragma unroll
-  for (int r = 0; r < K; ++r) fp_r[r] = sh[r][0];
-  // vote of the fingerprints (uniform across the workgroup)
+}
+
+__device__ __forceinline__ Walk make_walk(uint64_t blk, uint64_t block_bytes) {
+  Walk w;
+  w.nth = blockDim.x;
+  w.sub_bytes = 64u * w.nth;
+  w.nsub = (uint32_t)(block_bytes / w.sub_bytes);
+  w.lg_nsub = (uint32_t)ilog2(w.nsub);
+  w.boff = blk * block_bytes;
+  return w;
+}
+
+__global__ __launch_bounds__(kMaxT) void k_fingerprint(BlockVoteD b) {
+  __shared__ u32x4 lbuf[2][kSubChunks];
+  __shared__ uint64_t sw[4];
+  __shared__ uint64_t sroot[1][4];
+  const Walk w = make_walk(blockIdx.x, b.block_bytes);
+  walk_block<1, false>(b, w, lbuf, sw, sroot);
+  if (threadIdx.x == 0) b.fps[blockIdx.x] = lds_tree(sroot[0], w.nsub);
+}
+
+// ---- block vote ------------------------------------------------------------
+// Workspace accumulators: [0] disagree blocks, [1] fallback blocks,
+// [2] unresolved elements, [3..3+K) replica blocks; zero between calls.
+constexpr int kBlkAcc = 3 + FTV_MAX_K;
+
+// Vote of the K block fingerprints (uniform across the workgroup): the block
+// map byte (bit r: replica r differs from the source, bit 7: no majority) and
+// the source replica.
+template <int K>
+__device__ __forceinline__ uint32_t vote_fps(const uint64_t (&f)[K], int *src_out) {
   int M = 0, src = 0;
 #pragma unroll
   for (int r = 0; r < K; ++r) {
     int s = 0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) s += fp_r[r] == fp_r[j];
+    for (int j = 0; j < K; ++j) s += f[r] == f[j];
     if (s > M) {
       M = s;
       src = r;
@@ -271,74 +252,202 @@ __global__ __launch_bounds__(LPT == 4 ? 256 : (LPT == 2 ? 64 : 1024)) void k_vot
   }
   uint32_t bm = 0;
 #pragma unroll
-  for (int r = 0; r < K; ++r) bm |= (uint32_t)(fp_r[r] != fp_r[src]) << r;
-  const bool majority = 2 * M > K;
-  if (!majority) bm |= 0x80u;
-  if (majority && (bm & 1u) && mine) {  // replica 0 is not the majority: recopy
-    u32x4 v[4 * LPT];
-    load_leaves<LPT>(rep_ptr<K>(b, src), off, b.nbytes, whole, v);
-    put_piece<LPT>(b, off, v, whole, false);
+  for (int r = 0; r < K; ++r) bm |= (uint32_t)(f[r] != f[src]) << r;
+  if (2 * M <= K) bm |= 0x80u;
+  *src_out = src;
+  return bm;
+}
+
+// Pass 1 over whole blocks: fingerprints of the block in all k replicas, their
+// vote, the block map, and the restore.  Only a block whose majority
+// fingerprint differs from replica 0's is copied again, from the source
+// replica.  Blocks without a majority are left to pass 2, which rewrites their
+// consensus and mask.
+template <int K>
+__global__ __launch_bounds__(kMaxT) void k_vote_blocks(BlockVoteD b) {
+  __shared__ u32x4 lbuf[2][kSubChunks];
+  __shared__ uint64_t sw[4];
+  __shared__ uint64_t sroot[K][4];
+  const uint64_t blk = blockIdx.x;
+  const Walk w = make_walk(blk, b.block_bytes);
+  walk_block<K, true>(b, w, lbuf, sw, sroot);
+  if (threadIdx.x < (uint32_t)K) {
+    const uint32_t r = threadIdx.x;
+    const uint64_t f = lds_tree(sroot[r], w.nsub);
+    sroot[r][0] = f;
+    if (b.fps) b.fps[(uint64_t)r * b.nblocks + blk] = f;
   }
-  if (threadIdx.x == 0) {
-    b.blockmap[blk] = (uint8_t)bm;
-    if (bm & 0x7fu) atomicAdd((unsigned long long *)&b.acc[0], 1ull);
-    if (!majority) atomicAdd((unsigned long long *)&b.acc[1], 1ull);
-    for (int r = 0; r < K; ++r)
-      if ((bm >> r) & 1u) atomicAdd((unsigned long long *)&b.acc[3 + r], 1ull);
+  __syncthreads();
+  uint64_t f[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) f[r] = sroot[r][0];
+  int src = 0;
+  const uint32_t bm = vote_fps<K>(f, &src);
+  if (!(bm & 0x80u) && (bm & 1u)) {  // replica 0 is not the majority: recopy
+    const u32x4 *sp = reinterpret_cast<const u32x4 *>(
+        reinterpret_cast<const uint8_t *>(rep_ptr<K>(b, src)) + w.boff);
+    u32x4 *dp = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(b.cons) + w.boff);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(b.block_bytes / 16); i += w.nth)
+      st16(dp, i, ld16(sp, i), true);
+  }
+  if (threadIdx.x == 0) b.blockmap[blk] = (uint8_t)bm;
+}
+
+// ---- the partial last block: one leaf per thread, read directly ------------
+// (the buffer ends inside the block; bytes past the end hash as zero and are
+// never written)
+__device__ __forceinline__ uint64_t partial_block_root(const void *buf, uint64_t off, uint64_t nbytes,
+                                                       uint64_t *sh, u32x4 (&v)[4]) {
+  load_leaf(buf, off, nbytes, v);
+  const uint32_t nth = blockDim.x;
+  const uint64_t h = lane_tree(leaf_hash(v), 6);
+  if ((threadIdx.x & 63u) == 0) sh[threadIdx.x >> 6] = h;
+  __syncthreads();
+  uint64_t root = 0;
+  if (threadIdx.x == 0) root = lds_tree(sh, nth >> 6);
+  __syncthreads();
+  return root;
+}
+
+__global__ __launch_bounds__(1024) void k_fingerprint_partial(const void *buf, uint64_t nbytes,
+                                                              uint64_t block_bytes, uint64_t *fp_out,
+                                                              uint64_t blk) {
+  __shared__ uint64_t sh[16];
+  u32x4 v[4];
+  const uint64_t root = partial_block_root(buf, blk * block_bytes + 64ull * threadIdx.x, nbytes, sh, v);
+  if (threadIdx.x == 0) fp_out[blk] = root;
+}
+
+// Consensus piece of a lane of the partial block: its 64 bytes up to the end
+// of the buffer (a multiple of 4 bytes), and optionally the mask bytes of its
+// elements zeroed.
+__device__ __forceinline__ void put_partial(const BlockVoteD &b, uint64_t off, const u32x4 (&v)[4], bool mask_too) {
+  uint32_t *dst = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(b.cons) + off);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (off + 16ull * c + 0 < b.nbytes) dst[4 * c + 0] = v[c].x;
+    if (off + 16ull * c + 4 < b.nbytes) dst[4 * c + 1] = v[c].y;
+    if (off + 16ull * c + 8 < b.nbytes) dst[4 * c + 2] = v[c].z;
+    if (off + 16ull * c + 12 < b.nbytes) dst[4 * c + 3] = v[c].w;
+  }
+  if (mask_too && b.mask) {
+    const uint64_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4 : 8;
+    const uint64_t end = off + 64 < b.nbytes ? off + 64 : b.nbytes;
+    for (uint64_t e = off / es; e < end / es; ++e) b.mask[e] = 0;
   }
 }
 
-// Pass 2: element vote of every block without a fingerprint majority (a
-// grid-stride scan of the block map), then the last workgroup writes the
-// stats and clears the workspace.
+template <int K>
+__global__ __launch_bounds__(1024) void k_vote_block_partial(BlockVoteD b, uint64_t blk) {
+  __shared__ uint64_t sh[16];
+  __shared__ uint64_t s_fp[K];
+  const uint64_t off = blk * b.block_bytes + 64ull * threadIdx.x;
+  const bool mine = off < b.nbytes;
+#pragma unroll 1
+  for (int r = 0; r < K; ++r) {
+    u32x4 v[4];
+    const uint64_t root = partial_block_root(rep_ptr<K>(b, r), off, b.nbytes, sh, v);
+    if (r == 0 && mine) put_partial(b, off, v, true);
+    if (threadIdx.x == 0) {
+      s_fp[r] = root;
+      if (b.fps) b.fps[(uint64_t)r * b.nblocks + blk] = root;
+    }
+  }
+  __syncthreads();
+  uint64_t f[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) f[r] = s_fp[r];
+  int src = 0;
+  const uint32_t bm = vote_fps<K>(f, &src);
+  if (!(bm & 0x80u) && (bm & 1u) && mine) {
+    u32x4 v[4];
+    load_leaf(rep_ptr<K>(b, src), off, b.nbytes, v);
+    put_partial(b, off, v, false);
+  }
+  if (threadIdx.x == 0) b.blockmap[blk] = (uint8_t)bm;
+}
+
+// Pass 2: scan of the block map in chunks of `chunk` blocks (at most the
+// workgroup size, one byte per thread): the map's counts, and the element vote
+// over every block without a fingerprint majority, which the workgroup runs
+// block by block.  Per workgroup the non-zero counts go to the accumulators.
 template <int DT, int TOL, int K>
-__global__ __launch_bounds__(256) void k_blocks_fallback(BlockVoteD b) {
+__global__ __launch_bounds__(256) void k_blocks_scan(BlockVoteD b, uint32_t chunk) {
   using W = typename VT<DT>::W;
-  __shared__ uint64_t sh[16 * kNumCounters];
-  __shared__ uint32_t s_last;
   constexpr int NC = Acc<K>::NC;
-  const uint64_t per = b.block_bytes / sizeof(W);
-  const uint64_t n = b.nbytes / sizeof(W);
-  Acc<K> acc;
-  acc.zero();
+  __shared__ uint64_t sh[16 * kNumCounters];
+  __shared__ uint32_t s_cnt[kBlkAcc];
+  __shared__ uint32_t s_nfb;
+  __shared__ uint64_t s_list[256];
   // the block's task record lives in LDS: a local record indexed at run time
   // (the rare general vote does) would be placed in scratch memory
   __shared__ TaskD t;
-  for (uint64_t blk = blockIdx.x; blk < b.nblocks; blk += gridDim.x) {
-    if (!(b.blockmap[blk] & 0x80u)) continue;
-    const uint64_t e0 = blk * per;
-    const uint64_t ne = (e0 + per < n ? e0 + per : n) - e0;
+  const uint64_t per = b.block_bytes / sizeof(W);
+  const uint64_t n = b.nbytes / sizeof(W);
+  if (threadIdx.x < (uint32_t)kBlkAcc) s_cnt[threadIdx.x] = 0;
+  uint32_t c_dis = 0, c_fb = 0, c_rep[K];
+#pragma unroll
+  for (int r = 0; r < K; ++r) c_rep[r] = 0;
+  Acc<K> acc;
+  acc.zero();
+  for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < b.nblocks; base += (uint64_t)gridDim.x * chunk) {
+    const uint64_t blk = base + threadIdx.x;
+    const uint32_t bm = (threadIdx.x < chunk && blk < b.nblocks) ? b.blockmap[blk] : 0u;
+    c_dis += (bm & 0x7fu) != 0;
+    c_fb += bm >> 7;
+#pragma unroll
+    for (int r = 0; r < K; ++r) c_rep[r] += (bm >> r) & 1u;
+    if (!__syncthreads_or((int)(bm & 0x80u))) continue;
+    if (threadIdx.x == 0) s_nfb = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int r = 0; r < FTV_MAX_K; ++r)
-        t.rep[r] = r < K ? (const void *)(reinterpret_cast<const W *>(b.rep[r]) + e0) : nullptr;
-      t.cons = reinterpret_cast<W *>(b.cons) + e0;
-      t.mask = b.mask ? b.mask + e0 : nullptr;
-      t.stats = nullptr;
-      t.n = ne;
-      t.nvec = ne / Vec<W>::V;
-      t.tol = b.tol;
-      t.k = K;
+    if (bm & 0x80u) s_list[atomicAdd(&s_nfb, 1u)] = blk;
+    __syncthreads();
+    const uint32_t nfb = s_nfb;
+    for (uint32_t i = 0; i < nfb; ++i) {
+      const uint64_t e0 = s_list[i] * per;
+      const uint64_t ne = (e0 + per < n ? e0 + per : n) - e0;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int r = 0; r < FTV_MAX_K; ++r)
+          t.rep[r] = r < K ? (const void *)(reinterpret_cast<const W *>(b.rep[r]) + e0) : nullptr;
+        t.cons = reinterpret_cast<W *>(b.cons) + e0;
+        t.mask = b.mask ? b.mask + e0 : nullptr;
+        t.stats = nullptr;
+        t.n = ne;
+        t.nvec = ne / Vec<W>::V;
+        t.tol = b.tol;
+        t.k = K;
+      }
+      __syncthreads();
+      vote_range<DT, TOL, K, true, 1>(t, 0, t.nvec, acc, false);
+      vote_tail<DT, TOL, K>(t, acc);
     }
-    __syncthreads();
-    vote_range<DT, TOL, K, true, 1>(t, 0, t.nvec, acc, false);
-    vote_tail<DT, TOL, K>(t, acc);
   }
-  const uint64_t tot = block_total<K>(acc, sh);
+  const uint64_t tot = block_total<K>(acc, sh);  // thread NC-1: elements without a majority
+  if (c_dis) atomicAdd(&s_cnt[0], c_dis);
+  if (c_fb) atomicAdd(&s_cnt[1], c_fb);
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+    if (c_rep[r]) atomicAdd(&s_cnt[3 + r], c_rep[r]);
+  __syncthreads();
+  if (threadIdx.x < (uint32_t)(3 + K)) {
+    const uint32_t q = threadIdx.x;
+    const uint64_t v = q == 2 ? 0 : (uint64_t)s_cnt[q];
+    if (v) __hip_atomic_fetch_add(&b.acc[q], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (threadIdx.x == (uint32_t)(NC - 1) && tot)
-    atomicAdd((unsigned long long *)&b.acc[2], (unsigned long long)tot);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev = __hip_atomic_fetch_add(b.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev + 1 == gridDim.x;
-  }
-  __syncthreads();
-  if (!s_last || threadIdx.x != 0) return;
-  __threadfence();
+    __hip_atomic_fetch_add(&b.acc[2], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Verdict and stats record from the accumulators, which are cleared.
+template <int K>
+__global__ __launch_bounds__(64) void k_blocks_finalize(BlockVoteD b) {
+  if (threadIdx.x != 0) return;
   uint64_t a[kBlkAcc];
-  for (int i = 0; i < kBlkAcc; ++i)
+  for (int i = 0; i < kBlkAcc; ++i) {
     a[i] = __hip_atomic_load(&b.acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b.acc[i] = 0;
+  }
   ftv_block_stats *st = b.bstats;
   st->blocks = b.nblocks;
   st->disagree_blocks = a[0];
@@ -363,9 +472,6 @@ __global__ __launch_bounds__(256) void k_blocks_fallback(BlockVoteD b) {
     st->verdict = FTV_UNRESOLVED;
     st->winner = argmin;
   }
-  for (int i = 0; i < kBlkAcc; ++i)
-    __hip_atomic_store(&b.acc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(b.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_blocks_empty(ftv_block_stats *st) {
@@ -377,33 +483,39 @@ __global__ void k_blocks_empty(ftv_block_stats *st) {
   }
 }
 
+// Scan + finalize.  The chunk (blocks per workgroup step) is the largest power
+// of two up to 256 that still gives every CU two workgroups, so that a map
+// full of no-majority blocks still spreads their element votes over the chip.
 template <int DT, int TOL, int K>
-hipError_t launch_fallback(const BlockVoteD &b, int num_cus, hipStream_t s) {
-  uint64_t grid = (uint64_t)num_cus * 4;
-  if (grid > b.nblocks) grid = b.nblocks;
-  hipLaunchKernelGGL((k_blocks_fallback<DT, TOL, K>), dim3((uint32_t)grid), dim3(256), 0, s, b);
+hipError_t launch_scan(const BlockVoteD &b, int num_cus, hipStream_t s) {
+  uint64_t chunk = 256;
+  while (chunk > 1 && b.nblocks / chunk < (uint64_t)num_cus * 2) chunk >>= 1;
+  uint64_t grid = (b.nblocks + chunk - 1) / chunk;
+  if (grid > (uint64_t)num_cus * 4) grid = (uint64_t)num_cus * 4;
+  hipLaunchKernelGGL((k_blocks_scan<DT, TOL, K>), dim3((uint32_t)grid), dim3(256), 0, s, b, (uint32_t)chunk);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_blocks_finalize<K>), dim3(1), dim3(64), 0, s, b);
   return hipGetLastError();
 }
 
-// Leaves per lane: 4 when the block has at least 256 leaves, so that each
-// lane combines two tree levels in registers; smaller blocks keep one wave.
-inline int leaves_per_lane(uint64_t block_bytes) {
+// Threads of a whole-block workgroup: one leaf per thread per sub-chunk.
+inline uint32_t block_threads(uint64_t block_bytes) {
   const uint64_t leaves = block_bytes / 64;
-  return leaves >= 256 ? 4 : (leaves >= 128 ? 2 : 1);
+  return (uint32_t)(leaves < kMaxT ? leaves : kMaxT);
 }
 
-template <int K, int LPT>
-hipError_t launch_blocks_kl(const BlockVoteD &b, hipStream_t s) {
+template <int K>
+hipError_t launch_blocks_hash(const BlockVoteD &b, hipStream_t s) {
   const uint64_t nwhole = b.nbytes / b.block_bytes;
   if (nwhole) {
-    const dim3 grid((uint32_t)nwhole), block((uint32_t)(b.block_bytes / 64 / LPT));
-    hipLaunchKernelGGL((k_vote_blocks<K, LPT, true>), grid, block, 0, s, b, (uint64_t)0);
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL((k_vote_blocks<K>), dim3((uint32_t)nwhole), dim3(block_threads(b.block_bytes)), 0, s, b);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (nwhole < b.nblocks) {  // the partial last block
-    hipLaunchKernelGGL((k_vote_blocks<K, 1, false>), dim3(1), dim3((uint32_t)(b.block_bytes / 64)), 0, s,
-                       b, nwhole);
+    hipLaunchKernelGGL((k_vote_block_partial<K>), dim3(1), dim3((uint32_t)(b.block_bytes / 64)), 0, s, b,
+                       nwhole);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -411,19 +523,17 @@ hipError_t launch_blocks_kl(const BlockVoteD &b, hipStream_t s) {
 
 template <int K>
 hipError_t launch_blocks_k(const BlockVoteD &b, int num_cus, hipStream_t s) {
-  const int lpt = leaves_per_lane(b.block_bytes);
-  hipError_t e = lpt == 4 ? launch_blocks_kl<K, 4>(b, s)
-                          : (lpt == 2 ? launch_blocks_kl<K, 2>(b, s) : launch_blocks_kl<K, 1>(b, s));
+  const hipError_t e = launch_blocks_hash<K>(b, s);
   if (e != hipSuccess) return e;
   switch (b.dtype * 3 + b.tolkind) {
-    case FTV_F32 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_F32, FTV_TOL_EXACT, K>(b, num_cus, s);
-    case FTV_F32 * 3 + FTV_TOL_ULP: return launch_fallback<FTV_F32, FTV_TOL_ULP, K>(b, num_cus, s);
-    case FTV_F32 * 3 + FTV_TOL_REL: return launch_fallback<FTV_F32, FTV_TOL_REL, K>(b, num_cus, s);
-    case FTV_F64 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_F64, FTV_TOL_EXACT, K>(b, num_cus, s);
-    case FTV_F64 * 3 + FTV_TOL_ULP: return launch_fallback<FTV_F64, FTV_TOL_ULP, K>(b, num_cus, s);
-    case FTV_F64 * 3 + FTV_TOL_REL: return launch_fallback<FTV_F64, FTV_TOL_REL, K>(b, num_cus, s);
-    case FTV_I32 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_I32, FTV_TOL_EXACT, K>(b, num_cus, s);
-    case FTV_I64 * 3 + FTV_TOL_EXACT: return launch_fallback<FTV_I64, FTV_TOL_EXACT, K>(b, num_cus, s);
+    case FTV_F32 * 3 + FTV_TOL_EXACT: return launch_scan<FTV_F32, FTV_TOL_EXACT, K>(b, num_cus, s);
+    case FTV_F32 * 3 + FTV_TOL_ULP: return launch_scan<FTV_F32, FTV_TOL_ULP, K>(b, num_cus, s);
+    case FTV_F32 * 3 + FTV_TOL_REL: return launch_scan<FTV_F32, FTV_TOL_REL, K>(b, num_cus, s);
+    case FTV_F64 * 3 + FTV_TOL_EXACT: return launch_scan<FTV_F64, FTV_TOL_EXACT, K>(b, num_cus, s);
+    case FTV_F64 * 3 + FTV_TOL_ULP: return launch_scan<FTV_F64, FTV_TOL_ULP, K>(b, num_cus, s);
+    case FTV_F64 * 3 + FTV_TOL_REL: return launch_scan<FTV_F64, FTV_TOL_REL, K>(b, num_cus, s);
+    case FTV_I32 * 3 + FTV_TOL_EXACT: return launch_scan<FTV_I32, FTV_TOL_EXACT, K>(b, num_cus, s);
+    case FTV_I64 * 3 + FTV_TOL_EXACT: return launch_scan<FTV_I64, FTV_TOL_EXACT, K>(b, num_cus, s);
   }
   return hipErrorInvalidValue;
 }
@@ -434,19 +544,22 @@ hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_b
                               uint64_t *fp_out, hipStream_t s) {
   const uint64_t nblocks = (nbytes + block_bytes - 1) / block_bytes;
   if (nblocks == 0) return hipSuccess;
-  const int lpt = leaves_per_lane(block_bytes);
   const uint64_t nwhole = nbytes / block_bytes;
   if (nwhole) {
-    const dim3 grid((uint32_t)nwhole), block((uint32_t)(block_bytes / 64 / lpt));
-    const uint64_t z = 0;
-    if (lpt == 4) hipLaunchKernelGGL((k_fingerprint<4, true>), grid, block, 0, s, buf, nbytes, block_bytes, fp_out, z);
-    else if (lpt == 2) hipLaunchKernelGGL((k_fingerprint<2, true>), grid, block, 0, s, buf, nbytes, block_bytes, fp_out, z);
-    else hipLaunchKernelGGL((k_fingerprint<1, true>), grid, block, 0, s, buf, nbytes, block_bytes, fp_out, z);
-    hipError_t e = hipGetLastError();
+    BlockVoteD b;
+    memset(&b, 0, sizeof(b));
+    b.rep[0] = buf;
+    b.k = 1;
+    b.nbytes = nbytes;
+    b.block_bytes = block_bytes;
+    b.nblocks = nblocks;
+    b.fps = fp_out;
+    hipLaunchKernelGGL(k_fingerprint, dim3((uint32_t)nwhole), dim3(block_threads(block_bytes)), 0, s, b);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (nwhole < nblocks)  // the partial last block
-    hipLaunchKernelGGL((k_fingerprint<1, false>), dim3(1), dim3((uint32_t)(block_bytes / 64)), 0, s, buf, nbytes,
+    hipLaunchKernelGGL(k_fingerprint_partial, dim3(1), dim3((uint32_t)(block_bytes / 64)), 0, s, buf, nbytes,
                        block_bytes, fp_out, nwhole);
   return hipGetLastError();
 }

@@ -33,7 +33,7 @@ struct TaskD {
   TolD tol;
   uint32_t k;
   uint32_t spec;
-  uint32_t ntiles; // batched launch: tiles of this task
+  uint32_t ntiles; // batched launch: tiles of this task (host bookkeeping)
   uint32_t vec;    // 1 = 16-byte vector path, 0 = scalar path
 };
 
@@ -48,16 +48,17 @@ struct TileD {
 constexpr int kMaxGrid = 8192;     // per-task launch: workgroups (partials rows)
 constexpr int kNumCounters = 32;   // >= 21 pairs + 7 disagree + 1 no-majority
 
-// Device accumulators of the per-task launch and its ticket; both are left
-// zeroed by the last workgroup of every launch.
+// Device accumulators of the per-task launch, left zeroed by the launch's
+// finalize kernel.
 struct VoteWs {
   uint64_t *acc;     // [kNumCounters]
-  uint32_t *ticket;
 };
 
 int elem_size(int dtype);
 
 // ---- launchers (ftv_vote.hip) -------------------------------------------
+// The vote kernel followed by a one-workgroup finalize kernel on the same
+// stream (stats record from the accumulators, accumulators cleared).
 hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
 
 // A persistent launch over a queue of tiles.  Two ways to name the tiles:
@@ -70,18 +71,23 @@ struct BatchLaunch {
   const uint64_t *prefix;      // device, prefix mode
   const uint64_t *ntiles_dev;  // device: [0] = tiles, [1] = tasks
   uint64_t *acc;               // device [ntasks][kNumCounters]
-  uint32_t *task_done;         // device [ntasks]
   uint32_t *queue_head;        // device
   uint32_t block;
   uint32_t grid;
   uint32_t nt_stores;
   uint32_t tile_vecs;          // prefix mode
 };
+// A batched call is three kernels: zero (queue head, accumulators of
+// ntiles_dev[1] tasks), the persistent vote, finalize (every task's stats).
 hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchLaunch &b, hipStream_t s);
 // Serving: zero queue_head and the accumulators of slots[0..hdr[2]).
-hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, uint32_t *done,
-                             const uint32_t *slots, const uint64_t *hdr, hipStream_t s);
+hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const uint32_t *slots,
+                             const uint64_t *hdr, hipStream_t s);
+// Serving: stats records of the nfin slots listed in fin (host count).
+hipError_t launch_slots_finalize(const TaskD *tasks, const uint64_t *acc, const uint32_t *fin,
+                                 uint32_t nfin, hipStream_t s);
 
 // ---- fingerprints and block vote (ftv_blocks.hip) ----------------------
 hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_bytes,
@@ -102,8 +108,7 @@ struct BlockVoteD {
   void *cons;
   uint8_t *mask;          // may be null
   ftv_block_stats *bstats;
-  uint64_t *acc;          // device workspace [16]
-  uint32_t *ticket;       // device workspace, self-resetting
+  uint64_t *acc;          // device workspace [16], left zeroed by the finalize kernel
 };
 hipError_t launch_vote_blocks(const BlockVoteD &b, int num_cus, hipStream_t s);
 

@@ -9,10 +9,10 @@
 // are on the GPU joins the very next launch and its tiles share the machine
 // with theirs.  Two iterations are kept in flight on the server's stream so
 // the device never idles while the host builds the next table.  Per-request
-// counts live in slot accumulators that persist across iterations; the tile
-// that completes a request writes its stats record straight into host-mapped
-// memory, and the server thread observes completion through the iteration's
-// event.  Latency is measured from the request's scheduled arrival time.
+// counts live in slot accumulators that persist across iterations; after the
+// iteration that issues a request's last tile, a small finalize kernel writes
+// its stats record straight into host-mapped memory, and the server thread
+// observes completion through the iteration's event.  Latency is measured from the request's scheduled arrival time.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -118,7 +118,7 @@ struct Req {
 struct Iter {
   hipEvent_t ev{};
   bool busy = false;
-  char *h_buf = nullptr;  // [hdr 256 B][new slots u32 x max_slots][tiles]
+  char *h_buf = nullptr;  // [hdr 256 B][new slots u32 x max_slots][finishing slots u32 x max_slots][tiles]
   char *d_buf = nullptr;
   uint32_t *d_queue = nullptr;
   std::vector<uint64_t> finishing;
@@ -144,7 +144,6 @@ struct ftv_server {
   Arena arena;
   TaskD *d_tasks = nullptr, *h_tasks = nullptr;
   uint64_t *d_acc = nullptr;
-  uint32_t *d_done = nullptr;
   ftv_stats *h_stats = nullptr, *d_stats = nullptr;
   Iter ring[kRing];
   int ring_next = 0;
@@ -160,7 +159,7 @@ struct ftv_server {
 namespace {
 
 size_t iter_bytes(const ftv_server *s) {
-  return 256 + sizeof(uint32_t) * s->cfg.max_slots + sizeof(TileD) * kMaxIterTiles;
+  return 256 + 2 * sizeof(uint32_t) * s->cfg.max_slots + sizeof(TileD) * kMaxIterTiles;
 }
 
 void note_queue(ftv_server *s, int64_t now) {
@@ -241,10 +240,12 @@ bool has_work(const ftv_server *s) { return !s->active.empty() || !s->fp_wait.em
 // Build one iteration table (the next chunk of every active vote) and launch.
 int launch_iteration(ftv_server *s, Iter &it) {
   uint64_t *hdr = reinterpret_cast<uint64_t *>(it.h_buf);
+  const size_t slots_bytes = sizeof(uint32_t) * s->cfg.max_slots;
   uint32_t *hs = reinterpret_cast<uint32_t *>(it.h_buf + 256);
-  TileD *ht = reinterpret_cast<TileD *>(it.h_buf + 256 + sizeof(uint32_t) * s->cfg.max_slots);
+  uint32_t *hf = reinterpret_cast<uint32_t *>(it.h_buf + 256 + slots_bytes);
+  TileD *ht = reinterpret_cast<TileD *>(it.h_buf + 256 + 2 * slots_bytes);
   const uint64_t chunk_tiles = std::max<uint64_t>(1, s->cfg.chunk_bytes / (16ull * kTileVecs));
-  uint64_t nnew = 0, ntiles = 0, nreq = s->fp_wait.size();
+  uint64_t nnew = 0, nfin = 0, ntiles = 0, nreq = s->fp_wait.size();
   std::vector<uint64_t> still;
   for (uint64_t tk : s->active) {
     Req &r = s->reqs[tk];
@@ -265,33 +266,39 @@ int launch_iteration(ftv_server *s, Iter &it) {
     }
     r.issued += (uint32_t)take;
     nreq += take ? 1 : 0;
-    if (r.issued == r.ntiles) it.finishing.push_back(tk);
-    else still.push_back(tk);
+    if (r.issued == r.ntiles) {
+      it.finishing.push_back(tk);
+      hf[nfin++] = (uint32_t)r.slot;
+    } else {
+      still.push_back(tk);
+    }
   }
   s->active.swap(still);
   hdr[0] = ntiles;
   hdr[1] = s->cfg.max_slots;
   hdr[2] = nnew;
-  const size_t bytes = 256 + sizeof(uint32_t) * s->cfg.max_slots + sizeof(TileD) * ntiles;
+  hdr[3] = nfin;
+  const size_t bytes = 256 + 2 * slots_bytes + sizeof(TileD) * ntiles;
   HIPCHK(hipMemcpyAsync(it.d_buf, it.h_buf, bytes, hipMemcpyHostToDevice, s->stream));
   const uint64_t *d_hdr = reinterpret_cast<const uint64_t *>(it.d_buf);
   const uint32_t *d_slots = reinterpret_cast<const uint32_t *>(it.d_buf + 256);
-  HIPCHK(launch_slots_init(it.d_queue, s->d_acc, s->d_done, d_slots, d_hdr, s->stream));
+  const uint32_t *d_fin = reinterpret_cast<const uint32_t *>(it.d_buf + 256 + slots_bytes);
+  HIPCHK(launch_slots_init(it.d_queue, s->d_acc, d_slots, d_hdr, s->stream));
   if (ntiles) {
     BatchLaunch b;
     b.tasks = s->d_tasks;
-    b.tiles = reinterpret_cast<const TileD *>(it.d_buf + 256 + sizeof(uint32_t) * s->cfg.max_slots);
+    b.tiles = reinterpret_cast<const TileD *>(it.d_buf + 256 + 2 * slots_bytes);
     b.prefix = nullptr;  // table mode: the iteration lists its tiles
     b.tile_vecs = kTileVecs;
     b.ntiles_dev = d_hdr;
     b.acc = s->d_acc;
-    b.task_done = s->d_done;
     b.queue_head = it.d_queue;
     b.block = 256;
     b.grid = (uint32_t)std::min<uint64_t>((uint64_t)s->num_cus * 3, ntiles);
     b.nt_stores = 1;
     HIPCHK(launch_batch_vote(b, s->stream));
   }
+  HIPCHK(launch_slots_finalize(s->d_tasks, s->d_acc, d_fin, (uint32_t)nfin, s->stream));
   for (uint64_t tk : s->fp_wait) {
     Req &r = s->reqs[tk];
     if (r.rq.fp_bytes)
@@ -427,7 +434,6 @@ void destroy_server(ftv_server *s) {
   if (s->d_tasks) (void)hipFree(s->d_tasks);
   if (s->h_tasks) (void)hipHostFree(s->h_tasks);
   if (s->d_acc) (void)hipFree(s->d_acc);
-  if (s->d_done) (void)hipFree(s->d_done);
   if (s->h_stats) (void)hipHostFree(s->h_stats);
   s->arena.destroy();
   if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -459,7 +465,6 @@ int ftv_server_create(const ftv_server_cfg *cfg, ftv_server **out) {
             hipMalloc(&s->d_tasks, sizeof(TaskD) * ns) == hipSuccess &&
             hipHostMalloc(&s->h_tasks, sizeof(TaskD) * ns) == hipSuccess &&
             hipMalloc(&s->d_acc, sizeof(uint64_t) * kNumCounters * ns) == hipSuccess &&
-            hipMalloc(&s->d_done, sizeof(uint32_t) * ns) == hipSuccess &&
             hipHostMalloc(&s->h_stats, sizeof(ftv_stats) * ns, hipHostMallocMapped) == hipSuccess &&
             hipHostGetDevicePointer((void **)&s->d_stats, s->h_stats, 0) == hipSuccess;
   for (auto &it : s->ring)

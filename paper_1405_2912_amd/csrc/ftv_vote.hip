@@ -2,16 +2,17 @@
 //
 // Per-task launch: a grid-stride loop over tiles of 16-byte vectors; each
 // workgroup reduces its wave accumulators and adds the non-zero totals to the
-// launch's device accumulators; the last workgroup to finish (atomic ticket)
-// decides the verdict, writes the whole stats record and re-arms the
-// accumulators and the ticket for the next launch.
+// launch's device accumulators (most workgroups see no disagreement and add
+// nothing).  A one-workgroup finalize kernel on the same stream then decides
+// the verdict, writes the stats record and clears the accumulators: the
+// kernel boundary orders the counts before the verdict, so the vote kernel
+// needs neither a completion ticket nor device-scope fences.
 //
 // Batched launch: one persistent grid pulls tiles from an atomic queue over a
 // table of (task, vector range) entries; a tile may belong to any task, so the
 // body dispatches on the task's (value type, tolerance, k) code, a
 // workgroup-uniform branch.  Per tile the workgroup adds its non-zero counts
-// to the task's accumulators; the workgroup completing a task's last tile
-// writes the task's stats.
+// to the task's accumulators; a finalize kernel writes every task's stats.
 #include "ftv_internal.hpp"
 #include "ftv_vote_dev.hpp"
 
@@ -30,8 +31,6 @@ struct Unroll {
 template <int DT, int TOL, int K, bool VEC>
 __global__ __launch_bounds__(256) void k_vote_task(TaskD t, VoteWs ws) {
   __shared__ uint64_t sh[16 * kNumCounters];
-  __shared__ uint64_t s_tot[kNumCounters];
-  __shared__ uint32_t s_last;
   constexpr int U = Unroll<K>::value;
   constexpr int NC = Acc<K>::NC;
   Acc<K> acc;
@@ -44,38 +43,42 @@ __global__ __launch_bounds__(256) void k_vote_task(TaskD t, VoteWs ws) {
   if constexpr (VEC) {
     if (blockIdx.x == gridDim.x - 1) vote_tail<DT, TOL, K>(t, acc);
   }
-  // non-zero workgroup totals go into the launch's device accumulators (most
-  // workgroups see no disagreement and add nothing); the last workgroup to
-  // finish reads them, writes the stats record and clears them again
   const uint64_t tot = block_total<K>(acc, sh);
   if (threadIdx.x < (uint32_t)NC && tot != 0)
     __hip_atomic_fetch_add(&ws.acc[threadIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev =
-        __hip_atomic_fetch_add(ws.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// Stats record of one task from its accumulator row, by one workgroup of at
+// least kNumCounters threads; the row is cleared when `clear` is set.
+__device__ __forceinline__ void finalize_task(const TaskD &t, uint64_t *row, bool clear,
+                                              uint64_t *s_tot) {
   if (threadIdx.x < (uint32_t)kNumCounters) {
-    s_tot[threadIdx.x] =
-        __hip_atomic_load(&ws.acc[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&ws.acc[threadIdx.x], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_tot[threadIdx.x] = __hip_atomic_load(&row[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (clear) row[threadIdx.x] = 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    write_stats<K>(t.stats, s_tot, t.n);
-    __hip_atomic_store(ws.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    switch (t.k) {
+      case 2: write_stats<2>(t.stats, s_tot, t.n); break;
+      case 3: write_stats<3>(t.stats, s_tot, t.n); break;
+      case 4: write_stats<4>(t.stats, s_tot, t.n); break;
+      case 5: write_stats<5>(t.stats, s_tot, t.n); break;
+      case 6: write_stats<6>(t.stats, s_tot, t.n); break;
+      case 7: write_stats<7>(t.stats, s_tot, t.n); break;
+    }
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_vote_finalize(TaskD t, VoteWs ws) {
+  __shared__ uint64_t s_tot[kNumCounters];
+  finalize_task(t, ws.acc, true, s_tot);
 }
 
 // ---- batched persistent launch -------------------------------------------
 template <int DT, int TOL, int K>
 __device__ __forceinline__ void run_tile(const TaskD &t, const TileD &tile, const BatchLaunch &b,
-                                         uint64_t *sh, uint64_t *s_tot, uint32_t *s_last) {
+                                         uint64_t *sh) {
   constexpr int U = Unroll<K>::value;
   constexpr int NC = Acc<K>::NC;
   Acc<K> acc;
@@ -86,27 +89,11 @@ __device__ __forceinline__ void run_tile(const TaskD &t, const TileD &tile, cons
   uint64_t *tacc = b.acc + (uint64_t)tile.task * kNumCounters;
   if (threadIdx.x < (uint32_t)NC && tot != 0)
     __hip_atomic_fetch_add(&tacc[threadIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev = __hip_atomic_fetch_add(&b.task_done[tile.task], 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    *s_last = prev + 1 == t.ntiles;
-  }
-  __syncthreads();
-  if (*s_last) {
-    __threadfence();
-    if (threadIdx.x < (uint32_t)kNumCounters)
-      s_tot[threadIdx.x] =
-          __hip_atomic_load(&tacc[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x == 0) write_stats<K>(t.stats, s_tot, t.n);
-  }
 }
 
 #define FTV_CASE(DT, TOL, K)                                   \
   case spec_code(DT, TOL, K):                                  \
-    run_tile<DT, TOL, K>(t, tile, b, sh, s_tot, &s_last);      \
+    run_tile<DT, TOL, K>(t, tile, b, sh);                      \
     break;
 #define FTV_CASES_K(DT, TOL) \
   FTV_CASE(DT, TOL, 2)       \
@@ -118,8 +105,7 @@ __device__ __forceinline__ void run_tile(const TaskD &t, const TileD &tile, cons
 
 __global__ __launch_bounds__(512) void k_vote_batch(BatchLaunch b) {
   __shared__ uint64_t sh[16 * kNumCounters];
-  __shared__ uint64_t s_tot[kNumCounters];
-  __shared__ uint32_t s_tile, s_last;
+  __shared__ uint32_t s_tile;
   __shared__ TileD s_tl;
   const uint64_t ntiles = b.ntiles_dev[0];
   const uint64_t ntasks = b.ntiles_dev[1];
@@ -175,22 +161,38 @@ __global__ __launch_bounds__(256) void k_batch_zero(BatchLaunch b) {
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = gid; i < ntasks * kNumCounters; i += stride) b.acc[i] = 0;
-  for (uint64_t i = gid; i < ntasks; i += stride) b.task_done[i] = 0;
   if (gid == 0) *b.queue_head = 0;
+}
+
+// Stats of every task of the batch, one workgroup per task (grid-stride).
+__global__ __launch_bounds__(64) void k_batch_finalize(BatchLaunch b) {
+  __shared__ uint64_t s_tot[kNumCounters];
+  const uint64_t ntasks = b.ntiles_dev[1];
+  for (uint64_t i = blockIdx.x; i < ntasks; i += gridDim.x)
+    finalize_task(b.tasks[i], b.acc + i * kNumCounters, false, s_tot);
 }
 
 // Serving iterations: re-arm the tile queue and clear the accumulators of the
 // slots whose requests join in this iteration (slots[0..hdr[2]) ).
 __global__ __launch_bounds__(256) void k_slots_init(uint32_t *queue_head, uint64_t *acc,
-                                                    uint32_t *done, const uint32_t *slots,
-                                                    const uint64_t *hdr) {
+                                                    const uint32_t *slots, const uint64_t *hdr) {
   const uint64_t nnew = hdr[2];
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = gid; i < nnew * kNumCounters; i += stride)
     acc[(uint64_t)slots[i / kNumCounters] * kNumCounters + i % kNumCounters] = 0;
-  for (uint64_t i = gid; i < nnew; i += stride) done[slots[i]] = 0;
   if (gid == 0) *queue_head = 0;
+}
+
+// Serving iterations: stats of the slots whose requests finish in this one.
+__global__ __launch_bounds__(64) void k_slots_finalize(const TaskD *tasks, const uint64_t *acc,
+                                                       const uint32_t *fin, uint32_t nfin) {
+  __shared__ uint64_t s_tot[kNumCounters];
+  for (uint32_t i = blockIdx.x; i < nfin; i += gridDim.x) {
+    const uint32_t slot = fin[i];
+    finalize_task(tasks[slot], const_cast<uint64_t *>(acc) + (uint64_t)slot * kNumCounters, false,
+                  s_tot);
+  }
 }
 
 // ---- per-task dispatch -----------------------------------------------------
@@ -226,6 +228,9 @@ hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t
   if (cap > (uint64_t)kMaxGrid) cap = kMaxGrid;
   const uint32_t grid = (uint32_t)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
   hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(256), 0, s, t, ws);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_vote_finalize, dim3(1), dim3(64), 0, s, t, ws);
   return hipGetLastError();
 }
 
@@ -272,14 +277,27 @@ hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, uint32_t *done,
-                             const uint32_t *slots, const uint64_t *hdr, hipStream_t s) {
-  hipLaunchKernelGGL(k_slots_init, dim3(32), dim3(256), 0, s, queue_head, acc, done, slots, hdr);
+hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const uint32_t *slots,
+                             const uint64_t *hdr, hipStream_t s) {
+  hipLaunchKernelGGL(k_slots_init, dim3(32), dim3(256), 0, s, queue_head, acc, slots, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_slots_finalize(const TaskD *tasks, const uint64_t *acc, const uint32_t *fin,
+                                 uint32_t nfin, hipStream_t s) {
+  if (nfin == 0) return hipSuccess;
+  const uint32_t grid = nfin < 1024 ? nfin : 1024;
+  hipLaunchKernelGGL(k_slots_finalize, dim3(grid), dim3(64), 0, s, tasks, acc, fin, nfin);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s) {
   hipLaunchKernelGGL(k_vote_batch, dim3(b.grid), dim3(b.block), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_finalize, dim3(1024), dim3(64), 0, s, b);
   return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ def ctx(gpu):
     c.close()
 
 
-@pytest.mark.parametrize("bb", [4096, 8192, 65536])
+@pytest.mark.parametrize("bb", [4096, 8192, 16384, 32768, 65536])
 def test_fingerprint_parity(gpu, ctx, bb):
     import torch
     rng = np.random.default_rng(bb)
@@ -92,6 +92,29 @@ def test_block_vote_k_dtype_matrix(gpu, k):
         print(f"case: block vote k={k} {np.dtype(dtype).name} block={bb}", flush=True)
         _block_case(gpu, reps, tol_o, tol_f, bb)
         _block_case(gpu, reps, tol_o, tol_f, bb, want_fps=False, want_mask=False)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_block_vote_replica0_outlier(gpu, k):
+    """Replica 0 is the odd one out in some blocks (whole ones and the ragged
+    last one): the consensus of those blocks is re-copied from the source
+    replica; one more block has no fingerprint majority at all."""
+    for dtype, bb in ((np.float32, 32768), (np.int64, 65536), (np.float64, 4096)):
+        isz = np.dtype(dtype).itemsize
+        per = bb // isz
+        n = 5 * per + 136 // isz                       # five whole blocks + a partial one
+        kind = {np.float32: "f32", np.int64: "i64", np.float64: "f64"}[dtype]
+        base = synth.values(kind, synth.INTFULL if dtype == np.int64 else synth.NORMAL, 11, k, n)
+        reps = [base.copy() for _ in range(k)]
+        u = reps[0].view(np.uint32 if isz == 4 else np.uint64)
+        for i in (1 * per + 7, 3 * per + per - 1, 5 * per + 2):  # blocks 1, 3 and the partial one
+            u[i] ^= 1
+        for r in range(1, k):                          # block 4: every replica different
+            reps[r].view(np.uint32 if isz == 4 else np.uint64)[4 * per + 3 * r] ^= 4
+        tol_o, tol_f = (oracle.exact(), gpu.exact()) if dtype == np.int64 else (oracle.ulp(0), gpu.ulp(0))
+        print(f"case: block vote replica-0 outlier k={k} {np.dtype(dtype).name} block={bb}", flush=True)
+        ref = _block_case(gpu, reps, tol_o, tol_f, bb)
+        assert ref.replica_blocks[0] >= 3 and ref.fallback_blocks >= 1
 
 
 def test_block_vote_empty_and_tiny(gpu):
