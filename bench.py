@@ -265,6 +265,17 @@ def bench_blocks(ftv, ctx, side=16384, reps_timed=10):
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps_timed
+    # standalone fingerprints of one replica (2 GiB read, 8 bytes per block written)
+    fps1 = torch.empty(n // per, dtype=torch.int64, device=reps[0].device)
+    ftv.fingerprint(ctx, reps[0], 65536, out=fps1)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps_timed):
+        ftv.fingerprint(ctx, reps[0], 65536, out=fps1)
+    ev1.record()
+    torch.cuda.synchronize()
+    fp_ms = ev0.elapsed_time(ev1) / reps_timed
+    fp_ok = bool(torch.equal(fps1, out["fps"].view(torch.int64).view(5, -1)[0]))
     s = ftv.read_block_stats(out["bstats"])
     nblocks = n // per
     alg = 5 * n * 8 + n * 8 + n + 5 * nblocks * 8 + nblocks
@@ -275,7 +286,11 @@ def bench_blocks(ftv, ctx, side=16384, reps_timed=10):
            "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
            "blocks": s["blocks"], "disagree_blocks": s["disagree_blocks"],
            "fallback_blocks": s["fallback_blocks"], "unresolved_elems": s["unresolved_elems"],
-           "verdict": s["verdict"], "consensus_equals_clean_replica": restored}
+           "verdict": s["verdict"], "consensus_equals_clean_replica": restored,
+           "fingerprint": {"workload": f"one {n * 8 >> 30} GiB replica, 64 KiB blocks",
+                           "ms": round(fp_ms, 4), "gbps": round((n * 8 + nblocks * 8) / fp_ms / 1e6, 1),
+                           "hbm_frac": round((n * 8 + nblocks * 8) / fp_ms / 1e6 / HBM_PEAK_GBS, 4),
+                           "equals_block_vote_fps": fp_ok}}
     del reps, out
     torch.cuda.empty_cache()
     return res
