@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "replica GB/s voted on 1 MI355X and % of HBM peak; batched vs per-task; p99 latency"
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote.hip", "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
+KERNEL_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote_task.hpp", "paper_1405_2912_amd/csrc/ftv_vote_f32.hip",
+                  "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
 
 
 def log(*a):
@@ -51,7 +52,11 @@ def traffic_from_profile(name: str, launches_bytes_alg: float):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_hash") != kernel_hash(d.get("sources", KERNEL_SOURCES)):
+    # counters taken on other sources (a renamed or split file) or on an older
+    # revision of them do not describe the kernel that runs now
+    if d.get("sources") != KERNEL_SOURCES:
+        return None
+    if d.get("kernel_hash") != kernel_hash(KERNEL_SOURCES):
         return None
     return d.get("hbm_bytes_per_launch")
 

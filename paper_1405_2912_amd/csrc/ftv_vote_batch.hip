@@ -1,12 +1,5 @@
-// ftv_vote.hip -- per-task and batched (persistent) vote kernels for gfx950.
-//
-// Per-task launch: a grid-stride loop over tiles of 16-byte vectors; each
-// workgroup reduces its wave accumulators and adds the non-zero totals to the
-// launch's device accumulators (most workgroups see no disagreement and add
-// nothing).  A one-workgroup finalize kernel on the same stream then decides
-// the verdict, writes the stats record and clears the accumulators: the
-// kernel boundary orders the counts before the verdict, so the vote kernel
-// needs neither a completion ticket nor device-scope fences.
+// ftv_vote_batch.hip -- the batched (persistent) vote kernel for gfx950, the
+// serving iteration kernels, and the per-task dispatch by value type.
 //
 // Batched launch: one persistent grid pulls tiles from an atomic queue over a
 // table of (task, vector range) entries; a tile may belong to any task, so the
@@ -20,60 +13,6 @@ namespace ftv {
 namespace {
 
 using namespace dev;
-
-constexpr int kVoteWgPerCu = 2;
-
-template <int K>
-struct Unroll {
-  static constexpr int value = K <= 3 ? 2 : 1;
-};
-
-template <int DT, int TOL, int K, bool VEC>
-__global__ __launch_bounds__(256) void k_vote_task(TaskD t, VoteWs ws) {
-  __shared__ uint64_t sh[16 * kNumCounters];
-  constexpr int U = Unroll<K>::value;
-  constexpr int NC = Acc<K>::NC;
-  Acc<K> acc;
-  acc.zero();
-  const uint64_t tile = (uint64_t)blockDim.x * U;
-  for (uint64_t b = (uint64_t)blockIdx.x * tile; b < t.nvec; b += (uint64_t)gridDim.x * tile) {
-    const uint64_t e = b + tile < t.nvec ? b + tile : t.nvec;
-    vote_range<DT, TOL, K, VEC, U>(t, b, e, acc, true);
-  }
-  if constexpr (VEC) {
-    if (blockIdx.x == gridDim.x - 1) vote_tail<DT, TOL, K>(t, acc);
-  }
-  const uint64_t tot = block_total<K>(acc, sh);
-  if (threadIdx.x < (uint32_t)NC && tot != 0)
-    __hip_atomic_fetch_add(&ws.acc[threadIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Stats record of one task from its accumulator row, by one workgroup of at
-// least kNumCounters threads; the row is cleared when `clear` is set.
-__device__ __forceinline__ void finalize_task(const TaskD &t, uint64_t *row, bool clear,
-                                              uint64_t *s_tot) {
-  if (threadIdx.x < (uint32_t)kNumCounters) {
-    s_tot[threadIdx.x] = __hip_atomic_load(&row[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (clear) row[threadIdx.x] = 0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    switch (t.k) {
-      case 2: write_stats<2>(t.stats, s_tot, t.n); break;
-      case 3: write_stats<3>(t.stats, s_tot, t.n); break;
-      case 4: write_stats<4>(t.stats, s_tot, t.n); break;
-      case 5: write_stats<5>(t.stats, s_tot, t.n); break;
-      case 6: write_stats<6>(t.stats, s_tot, t.n); break;
-      case 7: write_stats<7>(t.stats, s_tot, t.n); break;
-    }
-  }
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(64) void k_vote_finalize(TaskD t, VoteWs ws) {
-  __shared__ uint64_t s_tot[kNumCounters];
-  finalize_task(t, ws.acc, true, s_tot);
-}
 
 // ---- batched persistent launch -------------------------------------------
 template <int DT, int TOL, int K>
@@ -195,79 +134,14 @@ __global__ __launch_bounds__(64) void k_slots_finalize(const TaskD *tasks, const
   }
 }
 
-// ---- per-task dispatch -----------------------------------------------------
-// Workgroups of this instance that fit on one CU at once.  The grid-stride
-// loop is only balanced when every workgroup of the grid is resident: a grid
-// larger than the machine leaves a second, mostly empty wave of workgroups.
-template <int DT, int TOL, int K, bool VEC>
-int resident_per_cu() {
-  static const int nb = [] {
-    int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_vote_task<DT, TOL, K, VEC>, 256, 0) !=
-            hipSuccess ||
-        v < 1) {
-      (void)hipGetLastError();
-      v = 4;
-    }
-    return v;
-  }();
-  return nb;
-}
-
-template <int DT, int TOL, int K, bool VEC>
-hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
-  constexpr int U = Unroll<K>::value;
-  const uint64_t tile = 256ull * U;
-  uint64_t tiles = (t.nvec + tile - 1) / tile;
-  // two workgroups per CU stream the replicas at the highest rate measured on
-  // MI355X (more concurrent streams lose DRAM page locality); never more than
-  // fit at once
-  const int per_cu = resident_per_cu<DT, TOL, K, VEC>() < kVoteWgPerCu ? resident_per_cu<DT, TOL, K, VEC>()
-                                                                       : kVoteWgPerCu;
-  uint64_t cap = (uint64_t)num_cus * per_cu;
-  if (cap > (uint64_t)kMaxGrid) cap = kMaxGrid;
-  const uint32_t grid = (uint32_t)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
-  hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(256), 0, s, t, ws);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_vote_finalize, dim3(1), dim3(64), 0, s, t, ws);
-  return hipGetLastError();
-}
-
-template <int DT, int TOL, bool VEC>
-hipError_t launch_k(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
-  switch (t.k) {
-    case 2: return launch_one<DT, TOL, 2, VEC>(t, ws, num_cus, s);
-    case 3: return launch_one<DT, TOL, 3, VEC>(t, ws, num_cus, s);
-    case 4: return launch_one<DT, TOL, 4, VEC>(t, ws, num_cus, s);
-    case 5: return launch_one<DT, TOL, 5, VEC>(t, ws, num_cus, s);
-    case 6: return launch_one<DT, TOL, 6, VEC>(t, ws, num_cus, s);
-    case 7: return launch_one<DT, TOL, 7, VEC>(t, ws, num_cus, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int DT, int TOL>
-hipError_t launch_vec(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
-  return t.vec ? launch_k<DT, TOL, true>(t, ws, num_cus, s)
-               : launch_k<DT, TOL, false>(t, ws, num_cus, s);
-}
-
 }  // namespace
 
 hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
-  const int dtype = (int)(t.spec / 24), tol = (int)((t.spec / 8) % 3);
-  switch (dtype) {
-    case FTV_F32:
-      if (tol == FTV_TOL_EXACT) return launch_vec<FTV_F32, FTV_TOL_EXACT>(t, ws, num_cus, s);
-      if (tol == FTV_TOL_ULP) return launch_vec<FTV_F32, FTV_TOL_ULP>(t, ws, num_cus, s);
-      return launch_vec<FTV_F32, FTV_TOL_REL>(t, ws, num_cus, s);
-    case FTV_F64:
-      if (tol == FTV_TOL_EXACT) return launch_vec<FTV_F64, FTV_TOL_EXACT>(t, ws, num_cus, s);
-      if (tol == FTV_TOL_ULP) return launch_vec<FTV_F64, FTV_TOL_ULP>(t, ws, num_cus, s);
-      return launch_vec<FTV_F64, FTV_TOL_REL>(t, ws, num_cus, s);
-    case FTV_I32: return launch_vec<FTV_I32, FTV_TOL_EXACT>(t, ws, num_cus, s);
-    case FTV_I64: return launch_vec<FTV_I64, FTV_TOL_EXACT>(t, ws, num_cus, s);
+  switch ((int)(t.spec / 24)) {
+    case FTV_F32: return launch_vote_task_f32(t, ws, num_cus, s);
+    case FTV_F64: return launch_vote_task_f64(t, ws, num_cus, s);
+    case FTV_I32: return launch_vote_task_i32(t, ws, num_cus, s);
+    case FTV_I64: return launch_vote_task_i64(t, ws, num_cus, s);
   }
   return hipErrorInvalidValue;
 }

@@ -654,5 +654,34 @@ __device__ __forceinline__ void write_stats(ftv_stats *st, const uint64_t *tot, 
   st->winner = winner;
 }
 
+// Vectors per lane and loop step of the streaming vote: two for k <= 3 (six
+// 16-byte loads in flight per lane), one for larger k.
+template <int K>
+struct Unroll {
+  static constexpr int value = K <= 3 ? 2 : 1;
+};
+
+// Stats record of one task from its accumulator row, by one workgroup of at
+// least kNumCounters threads; the row is cleared when `clear` is set.
+__device__ __forceinline__ void finalize_task(const TaskD &t, uint64_t *row, bool clear,
+                                              uint64_t *s_tot) {
+  if (threadIdx.x < (uint32_t)kNumCounters) {
+    s_tot[threadIdx.x] = __hip_atomic_load(&row[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (clear) row[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    switch (t.k) {
+      case 2: write_stats<2>(t.stats, s_tot, t.n); break;
+      case 3: write_stats<3>(t.stats, s_tot, t.n); break;
+      case 4: write_stats<4>(t.stats, s_tot, t.n); break;
+      case 5: write_stats<5>(t.stats, s_tot, t.n); break;
+      case 6: write_stats<6>(t.stats, s_tot, t.n); break;
+      case 7: write_stats<7>(t.stats, s_tot, t.n); break;
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace dev
 }  // namespace ftv

@@ -1,0 +1,10 @@
+// ftv_vote_i64.hip -- per-task vote kernels for i64 values (see ftv_vote_task.hpp).
+#include "ftv_vote_task.hpp"
+
+namespace ftv {
+
+hipError_t launch_vote_task_i64(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+  return launch_vec<FTV_I64, FTV_TOL_EXACT>(t, ws, num_cus, s);
+}
+
+}  // namespace ftv
