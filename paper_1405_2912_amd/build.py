@@ -57,7 +57,9 @@ def build(jobs: int = 4) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    # only the C ABI (ftv_*) is exported; internal C++ symbols stay local
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread",
+           f"-Wl,--version-script={os.path.join(CSRC, 'ftv.map')}"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"linking libftv.so failed:\n{res.stderr[-4000:]}")

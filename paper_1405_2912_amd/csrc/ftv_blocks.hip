@@ -371,14 +371,24 @@ __global__ __launch_bounds__(1024) void k_vote_block_partial(BlockVoteD b, uint6
 // workgroup size, one byte per thread): the map's counts, and the element vote
 // over every block without a fingerprint majority, which the workgroup runs
 // block by block.  Per workgroup the non-zero counts go to the accumulators.
+// The workgroup is wide (1024 threads, several vectors per lane for small k)
+// so that a 64 KiB block takes one or two passes: a lone no-majority block is
+// a latency chain of passes, not a bandwidth problem.
+constexpr uint32_t kScanThreads = 1024;
+
+template <int K>
+struct ScanUnroll {
+  static constexpr int value = K <= 2 ? 4 : (K <= 4 ? 2 : 1);
+};
+
 template <int DT, int TOL, int K>
-__global__ __launch_bounds__(256) void k_blocks_scan(BlockVoteD b, uint32_t chunk) {
+__global__ __launch_bounds__(kScanThreads) void k_blocks_scan(BlockVoteD b, uint32_t chunk) {
   using W = typename VT<DT>::W;
   constexpr int NC = Acc<K>::NC;
   __shared__ uint64_t sh[16 * kNumCounters];
   __shared__ uint32_t s_cnt[kBlkAcc];
   __shared__ uint32_t s_nfb;
-  __shared__ uint64_t s_list[256];
+  __shared__ uint64_t s_list[kScanThreads];
   // the block's task record lives in LDS: a local record indexed at run time
   // (the rare general vote does) would be placed in scratch memory
   __shared__ TaskD t;
@@ -419,7 +429,7 @@ __global__ __launch_bounds__(256) void k_blocks_scan(BlockVoteD b, uint32_t chun
         t.k = K;
       }
       __syncthreads();
-      vote_range<DT, TOL, K, true, 1>(t, 0, t.nvec, acc, false);
+      vote_range<DT, TOL, K, true, ScanUnroll<K>::value>(t, 0, t.nvec, acc, false);
       vote_tail<DT, TOL, K>(t, acc);
     }
   }
@@ -484,15 +494,17 @@ __global__ void k_blocks_empty(ftv_block_stats *st) {
 }
 
 // Scan + finalize.  The chunk (blocks per workgroup step) is the largest power
-// of two up to 256 that still gives every CU two workgroups, so that a map
-// full of no-majority blocks still spreads their element votes over the chip.
+// of two up to the workgroup size that still gives every CU two workgroups, so
+// that a map full of no-majority blocks still spreads their element votes over
+// the chip.
 template <int DT, int TOL, int K>
 hipError_t launch_scan(const BlockVoteD &b, int num_cus, hipStream_t s) {
-  uint64_t chunk = 256;
+  uint64_t chunk = kScanThreads;
   while (chunk > 1 && b.nblocks / chunk < (uint64_t)num_cus * 2) chunk >>= 1;
   uint64_t grid = (b.nblocks + chunk - 1) / chunk;
-  if (grid > (uint64_t)num_cus * 4) grid = (uint64_t)num_cus * 4;
-  hipLaunchKernelGGL((k_blocks_scan<DT, TOL, K>), dim3((uint32_t)grid), dim3(256), 0, s, b, (uint32_t)chunk);
+  if (grid > (uint64_t)num_cus * 2) grid = (uint64_t)num_cus * 2;
+  hipLaunchKernelGGL((k_blocks_scan<DT, TOL, K>), dim3((uint32_t)grid), dim3(kScanThreads), 0, s, b,
+                     (uint32_t)chunk);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_blocks_finalize<K>), dim3(1), dim3(64), 0, s, b);

@@ -38,6 +38,10 @@ def test_no_unexpected_exports():
     out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True).stdout
     exported = sorted({ln.split()[-1] for ln in out.splitlines() if " T ftv_" in ln})
     assert exported == _declared()
+    # nothing but the C ABI is visible: internal C++ symbols are local
+    others = sorted({ln.split()[-1] for ln in out.splitlines()
+                     if ln.split() and not ln.split()[-1].startswith("ftv_")})
+    assert others == [], others[:10]
 
 
 def _c_sizes():
