@@ -302,6 +302,55 @@ def bench_blocks(ftv, ctx, side=16384, reps_timed=10):
 
 
 # ---------------------------------------------------------------------------
+# siblings: fault-tolerant memory management of a 2 GiB checkpoint area
+# ---------------------------------------------------------------------------
+def bench_siblings(ftv, gib: int = 2):
+    import numpy as np
+    import torch
+    nbytes = gib << 30
+    log(f"bench: siblings of a {gib} GiB host area")
+    host = (np.arange(nbytes // 8, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)).view(np.uint8)
+    mm = ftv.MemoryManager(device=0, fault_tolerant=True)
+    a = mm.register(host)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    # first device use: a new device sibling, copied from the host area
+    (_, s_w), h2d_ms = timed(lambda: mm.request(a, ftv.MEM_DEVICE, ftv.ACC_WRITE, stream))
+    mm.release(a, s_w, True)                      # the kernel "succeeded": version 2
+    # a read on the device while the only newest copy is there: a backup copy
+    (_, s_r), d2d_ms = timed(lambda: mm.request(a, ftv.MEM_DEVICE, ftv.ACC_READ, stream))
+    mm.release(a, s_r, True)
+    # validation of the two device siblings by fingerprints (no data moved)
+    mm.check(a, 65536, stream)
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = mm.check(a, 65536, stream)
+    check_ms = (time.perf_counter() - t0) * 1e3 / reps
+    # the result back into the registered host area
+    (_, s_h), d2h_ms = timed(lambda: mm.request(a, ftv.MEM_HOST, ftv.ACC_READ, stream))
+    mm.release(a, s_h, True)
+    table = mm.siblings(a)
+    mm.close()
+    return {"workload": f"{gib} GiB area registered in pageable host memory, fault-tolerant mode",
+            "h2d_ms": round(h2d_ms, 2), "h2d_gbps": round(nbytes / h2d_ms / 1e6, 1),
+            "backup_d2d_ms": round(d2d_ms, 3), "backup_d2d_gbps": round(2 * nbytes / d2d_ms / 1e6, 1),
+            "check_ms": round(check_ms, 3), "check_siblings": r["checked"],
+            "check_gbps": round(r["checked"] * nbytes / check_ms / 1e6, 1),
+            "check_hbm_frac": round(r["checked"] * nbytes / check_ms / 1e6 / HBM_PEAK_GBS, 4),
+            "d2h_ms": round(d2h_ms, 2), "d2h_gbps": round(nbytes / d2h_ms / 1e6, 1),
+            "final_versions": [t["version"] for t in table], "all_valid": all(t["valid"] for t in table)}
+
+
+# ---------------------------------------------------------------------------
 # serving: Poisson arrivals, continuous batching, p50/p99 latency
 # ---------------------------------------------------------------------------
 def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0):
@@ -425,6 +474,7 @@ def main():
     if not args.main_only:
         out["batched"] = bench_batched(ftv, ctx, args.batch_tasks)
         out["blocks"] = bench_blocks(ftv, ctx)
+        out["siblings"] = bench_siblings(ftv)
         out["serving"] = bench_serving(ftv, ctx, args.serve_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -331,6 +331,96 @@ int ftv_rank_units(const ftv_unit *units, uint32_t n, int probe, uint32_t *order
 int ftv_record_vote(ftv_unit *units, uint32_t nunits, const uint32_t *unit_of_replica, uint32_t k,
                     const ftv_stats *stats);
 
+/* ---- memory areas with siblings and versions (Sec. IV-A, IV-C) ------------ *
+ * The runtime's memory management: a registered area has copies ("siblings")
+ * in host memory and in device memory, each tagged with a version that is
+ * increased by one on write access.  A request for the area in some memory
+ * returns a sibling there holding the highest version, copying the data into
+ * a new (or stale, reused) sibling when that memory has none.  In
+ * fault-tolerant mode a request is only served by an existing sibling when
+ * another highest-version sibling exists as well; otherwise a new sibling is
+ * created and returned, so the previous one survives as the backup.  A kernel
+ * that ran into a fault releases its sibling with ok = 0, which invalidates
+ * it; the next request copies from a valid sibling (Fig. 1).  ftv_mm_check
+ * compares the highest-version siblings by block fingerprints and invalidates
+ * those that differ from a strict majority -- validation of backups without
+ * moving them.
+ *
+ * Readings where the paper is silent: a new sibling reuses the lowest-indexed
+ * stale or invalid sibling not in use in that memory before allocating
+ * (sibling 0 is the caller's registered host area, so a host request brings
+ * the newest data back into it); among candidates the lowest index wins and a
+ * copy source in the requested memory is preferred; a sibling handed out for
+ * writing is neither a candidate nor a copy source until released, and a
+ * write never gets a sibling that has readers; a release with ok = 0
+ * invalidates the sibling whatever the access.
+ *
+ * All calls on one manager are serialised internally (thread-safe).  Copies
+ * into device siblings are enqueued on `stream`; a request for host memory
+ * synchronises `stream` before it returns. */
+typedef struct ftv_mm ftv_mm;
+
+#define FTV_MEM_HOST 0
+#define FTV_MEM_DEVICE 1
+#define FTV_ACC_READ 1
+#define FTV_ACC_WRITE 2
+#define FTV_ACC_READWRITE 3
+#define FTV_MM_MAX_SIBLINGS 64
+
+typedef struct ftv_sibling_info {
+  void *ptr;           /* host or device address of the sibling's bytes */
+  int32_t memory;      /* FTV_MEM_HOST or FTV_MEM_DEVICE */
+  int32_t valid;       /* 0 after a release with ok = 0 or a failed check */
+  uint64_t version;    /* 1 at registration; +1 per successful write */
+  uint32_t readers;    /* requests for reading not yet released */
+  int32_t writing;     /* handed out for writing, not yet released */
+  int32_t caller;      /* 1 for sibling 0, the caller's registered area */
+  uint32_t reserved;
+} ftv_sibling_info;
+
+typedef struct ftv_mm_check_result {
+  uint32_t checked;        /* highest-version siblings compared */
+  uint32_t invalidated;    /* of those, marked invalid */
+  uint64_t unresolved;     /* blocks without a strict majority fingerprint */
+  uint64_t blocks;         /* blocks per sibling */
+} ftv_mm_check_result;
+
+/* device >= 0: siblings in that device's memory; device = -1: host memory
+ * only (no HIP call is made; device requests and ftv_mm_check fail).
+ * fault_tolerant: 0 or 1 (the rules above).  FTV_E_INVALID, FTV_E_HIP,
+ * FTV_E_NOMEM. */
+int ftv_mm_create(int device, int fault_tolerant, ftv_mm **out);
+/* Frees every sibling the manager allocated (never the registered areas). */
+int ftv_mm_destroy(ftv_mm *mm);
+/* Register the caller's host area (host_ptr, bytes > 0; it stays owned by the
+ * caller and must outlive the manager) as sibling 0 at version 1.  *area
+ * receives its handle. */
+int ftv_mm_register(ftv_mm *mm, void *host_ptr, uint64_t bytes, uint32_t *area);
+/* Request the area in `memory` for `access` (FTV_ACC_*): *ptr receives the
+ * sibling's address (valid for work on `stream` after this call), *sibling its
+ * index for ftv_mm_release.  FTV_E_BUSY when the only highest-version siblings
+ * are being written; FTV_E_INVALID when no valid sibling is left (every copy
+ * failed: re-register the input) or on bad arguments; FTV_E_NOMEM when a new
+ * sibling cannot be allocated or FTV_MM_MAX_SIBLINGS is reached. */
+int ftv_mm_request(ftv_mm *mm, uint32_t area, int memory, int access, void *stream, void **ptr,
+                   uint32_t *sibling);
+/* End the use of a sibling obtained from ftv_mm_request.  ok = 1: a write
+ * makes the sibling the newest (version = highest + 1); a read just ends.
+ * ok = 0: a fault was detected while the sibling was in use; it becomes
+ * invalid.  The caller must have synchronised the work that used it. */
+int ftv_mm_release(ftv_mm *mm, uint32_t area, uint32_t sibling, int ok);
+/* Copy the sibling table of an area into out[0 .. min(cap, count)) (host);
+ * *count receives the number of siblings. */
+int ftv_mm_siblings(ftv_mm *mm, uint32_t area, ftv_sibling_info *out, uint32_t cap, uint32_t *count);
+/* Fingerprint every valid highest-version sibling not being written (host
+ * siblings through a device staging copy) in blocks of block_bytes (a power of
+ * two in [4096, 65536], the definition of ftv_fingerprint), vote per block,
+ * and invalidate the siblings that differ from a strict majority in some
+ * block.  Synchronises `stream`.  Fewer than two such siblings: nothing is
+ * compared.  *out (host) receives the counts. */
+int ftv_mm_check(ftv_mm *mm, uint32_t area, uint64_t block_bytes, void *stream,
+                 ftv_mm_check_result *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,11 +93,24 @@ class Unit(Structure):
     _fields_ = [("runtime", c_double), ("valid", c_uint64), ("total", c_uint64)]
 
 
+class SiblingInfo(Structure):
+    _fields_ = [("ptr", c_void_p), ("memory", c_int32), ("valid", c_int32), ("version", c_uint64),
+                ("readers", c_uint32), ("writing", c_int32), ("caller", c_int32),
+                ("reserved", c_uint32)]
+
+
+class MMCheckResult(Structure):
+    _fields_ = [("checked", c_uint32), ("invalidated", c_uint32), ("unresolved", c_uint64),
+                ("blocks", c_uint64)]
+
+
 EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv_ctx_destroy",
            "ftv_vote", "ftv_vote_batch", "ftv_batch_get_config", "ftv_batch_set_config",
            "ftv_tune_batch", "ftv_fingerprint", "ftv_vote_blocks", "ftv_server_create",
            "ftv_submit", "ftv_poll", "ftv_release", "ftv_server_get_stats",
-           "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote"]
+           "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote",
+           "ftv_mm_create", "ftv_mm_destroy", "ftv_mm_register", "ftv_mm_request", "ftv_mm_release",
+           "ftv_mm_siblings", "ftv_mm_check"]
 
 _lib = None
 
@@ -135,6 +148,13 @@ def load():
     L.ftv_fault_aware_runtime.argtypes = [POINTER(Unit)]
     L.ftv_rank_units.argtypes = [POINTER(Unit), c_uint32, c_int, POINTER(c_uint32)]
     L.ftv_record_vote.argtypes = [POINTER(Unit), c_uint32, POINTER(c_uint32), c_uint32, POINTER(Stats)]
+    L.ftv_mm_create.argtypes = [c_int, c_int, POINTER(vp)]
+    L.ftv_mm_destroy.argtypes = [vp]
+    L.ftv_mm_register.argtypes = [vp, vp, c_uint64, POINTER(c_uint32)]
+    L.ftv_mm_request.argtypes = [vp, c_uint32, c_int, c_int, vp, POINTER(vp), POINTER(c_uint32)]
+    L.ftv_mm_release.argtypes = [vp, c_uint32, c_uint32, c_int]
+    L.ftv_mm_siblings.argtypes = [vp, c_uint32, POINTER(SiblingInfo), c_uint32, POINTER(c_uint32)]
+    L.ftv_mm_check.argtypes = [vp, c_uint32, c_uint64, vp, POINTER(MMCheckResult)]
     for name in EXPORTS:
         fn = getattr(L, name, None)
         if fn is not None and name not in ("ftv_version", "ftv_last_error", "ftv_now_ns",
@@ -425,3 +445,74 @@ def record_vote(units, unit_of_replica, stats: Stats):
     k = len(unit_of_replica)
     u = (c_uint32 * k)(*unit_of_replica)
     _check(load().ftv_record_vote(units, len(units), u, k, ctypes.byref(stats)))
+
+
+# ---- memory areas with siblings and versions ----------------------------------
+MEM_HOST, MEM_DEVICE = 0, 1
+ACC_READ, ACC_WRITE, ACC_READWRITE = 1, 2, 3
+
+
+class MemoryManager:
+    """Siblings and versions of registered host areas (the C calls ftv_mm_*).
+    device = -1 makes a host-only manager (no HIP call)."""
+
+    def __init__(self, device: int = 0, fault_tolerant: bool = True):
+        h = c_void_p()
+        _check(load().ftv_mm_create(int(device), int(bool(fault_tolerant)), ctypes.byref(h)))
+        self.handle = h
+        self.device = int(device)
+        self._held = []   # registered host buffers stay alive with the manager
+
+    def _stream(self, stream) -> int:
+        # a host-only manager makes no HIP call: it needs no stream (and no GPU)
+        if stream is None and self.device < 0:
+            return 0
+        return _stream_handle(stream)
+
+    def register(self, host_array) -> int:
+        """Register a C-contiguous numpy array (the caller's area, sibling 0)."""
+        if not host_array.flags["C_CONTIGUOUS"]:
+            raise ValueError("the area must be C-contiguous")
+        self._held.append(host_array)
+        a = c_uint32()
+        _check(load().ftv_mm_register(self.handle, c_void_p(host_array.ctypes.data), host_array.nbytes,
+                                      ctypes.byref(a)))
+        return int(a.value)
+
+    def request(self, area: int, memory: int, access: int, stream=None):
+        """-> (address, sibling index)."""
+        p, sib = c_void_p(), c_uint32()
+        _check(load().ftv_mm_request(self.handle, area, memory, access,
+                                     c_void_p(self._stream(stream)), ctypes.byref(p),
+                                     ctypes.byref(sib)))
+        return int(p.value or 0), int(sib.value)
+
+    def release(self, area: int, sibling: int, ok: bool = True):
+        _check(load().ftv_mm_release(self.handle, area, sibling, int(bool(ok))))
+
+    def siblings(self, area: int):
+        n = c_uint32()
+        _check(load().ftv_mm_siblings(self.handle, area, None, 0, ctypes.byref(n)))
+        arr = (SiblingInfo * max(1, n.value))()
+        _check(load().ftv_mm_siblings(self.handle, area, arr, n.value, ctypes.byref(n)))
+        return [{"ptr": int(s.ptr or 0), "memory": int(s.memory), "valid": bool(s.valid),
+                 "version": int(s.version), "readers": int(s.readers), "writing": bool(s.writing),
+                 "caller": bool(s.caller)} for s in arr[:n.value]]
+
+    def check(self, area: int, block_bytes: int = 65536, stream=None) -> dict:
+        r = MMCheckResult()
+        _check(load().ftv_mm_check(self.handle, area, block_bytes, c_void_p(self._stream(stream)),
+                                   ctypes.byref(r)))
+        return {"checked": int(r.checked), "invalidated": int(r.invalidated),
+                "unresolved": int(r.unresolved), "blocks": int(r.blocks)}
+
+    def close(self):
+        if self.handle:
+            load().ftv_mm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

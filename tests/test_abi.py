@@ -51,11 +51,13 @@ def _c_sizes():
 #include <stdio.h>
 #include "ftv.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ftv_tol), sizeof(ftv_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ftv_tol), sizeof(ftv_stats),
          sizeof(ftv_vote_desc), sizeof(ftv_batch_cfg), sizeof(ftv_block_stats),
-         sizeof(ftv_server_cfg), sizeof(ftv_request), sizeof(ftv_result), sizeof(ftv_server_stats));
-  printf("%zu %zu %zu %zu\n", offsetof(ftv_stats, verdict), offsetof(ftv_vote_desc, tol),
-         offsetof(ftv_vote_desc, stats), offsetof(ftv_request, t_arrival_ns));
+         sizeof(ftv_server_cfg), sizeof(ftv_request), sizeof(ftv_result), sizeof(ftv_server_stats),
+         sizeof(ftv_sibling_info), sizeof(ftv_mm_check_result));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(ftv_stats, verdict), offsetof(ftv_vote_desc, tol),
+         offsetof(ftv_vote_desc, stats), offsetof(ftv_request, t_arrival_ns),
+         offsetof(ftv_sibling_info, readers), offsetof(ftv_mm_check_result, blocks));
   return 0;
 }
 '''
@@ -73,10 +75,12 @@ def test_ctypes_layout_matches_c():
     import paper_1405_2912_amd.ftv as b
     sizes, offs = _c_sizes()
     mine = [ctypes.sizeof(t) for t in (b.Tol, b.Stats, b.VoteDesc, b.BatchCfg, b.BlockStats,
-                                       b.ServerCfg, b.Request, b.Result, b.ServerStats)]
+                                       b.ServerCfg, b.Request, b.Result, b.ServerStats,
+                                       b.SiblingInfo, b.MMCheckResult)]
     assert mine == sizes
     assert [b.Stats.verdict.offset, b.VoteDesc.tol.offset, b.VoteDesc.stats.offset,
-            b.Request.t_arrival_ns.offset] == offs
+            b.Request.t_arrival_ns.offset, b.SiblingInfo.readers.offset,
+            b.MMCheckResult.blocks.offset] == offs
 
 
 def test_host_validation_without_gpu(lib):
