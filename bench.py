@@ -324,8 +324,16 @@ def bench_siblings(ftv, gib: int = 2):
     # first device use: a new device sibling, copied from the host area
     (_, s_w), h2d_ms = timed(lambda: mm.request(a, ftv.MEM_DEVICE, ftv.ACC_WRITE, stream))
     mm.release(a, s_w, True)                      # the kernel "succeeded": version 2
-    # a read on the device while the only newest copy is there: a backup copy
-    (_, s_r), d2d_ms = timed(lambda: mm.request(a, ftv.MEM_DEVICE, ftv.ACC_READ, stream))
+    # a read on the device while the only newest copy is there: a backup copy.
+    # The first one allocates the sibling; to time the copy alone, the backup
+    # is then failed (released with ok = 0) and made again into the same slot.
+    (_, s_r), _ = timed(lambda: mm.request(a, ftv.MEM_DEVICE, ftv.ACC_READ, stream))
+    d2d = []
+    for _ in range(3):
+        mm.release(a, s_r, False)
+        (_, s_r), ms = timed(lambda: mm.request(a, ftv.MEM_DEVICE, ftv.ACC_READ, stream))
+        d2d.append(ms)
+    d2d_ms = min(d2d)
     mm.release(a, s_r, True)
     # validation of the two device siblings by fingerprints (no data moved)
     mm.check(a, 65536, stream)

@@ -168,9 +168,12 @@ typedef struct ftv_batch_cfg {
 int ftv_batch_get_config(ftv_ctx *ctx, ftv_batch_cfg *out);
 /* FTV_E_INVALID if a field is out of range. */
 int ftv_batch_set_config(ftv_ctx *ctx, const ftv_batch_cfg *cfg);
-/* Autotuner: times every candidate schedule on this batch (`iters` timed runs
- * each, on `stream`, synchronising it), installs the fastest in the context and
- * writes it to *best (may be NULL).  The batch's outputs hold a valid result
+/* Autotuner: coordinate descent from the context's current schedule over tile
+ * size, block size, grid multiple, order and store kind, two passes, each
+ * candidate timed on this batch (fastest of `iters` runs after a warm one, on
+ * `stream`, synchronising it); the winner is re-timed against the starting
+ * schedule and the faster one is installed in the context and written to
+ * *best (may be NULL).  The batch's outputs hold a valid result
  * afterwards.  If the environment variable FTV_TUNE_CACHE names a file, the
  * choice is stored there as JSON keyed by device name, CU count and a coarse
  * signature of the batch, and reused by ftv_tune_batch on a cache hit. */

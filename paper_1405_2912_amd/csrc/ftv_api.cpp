@@ -457,12 +457,14 @@ int ftv_tune_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  auto time_cfg = [&](const ftv_batch_cfg &cfg, double *ms) -> int {
+  // the fastest of `n` timed runs after a warm one: interference only ever
+  // adds time, so the minimum is the steadiest estimate of a schedule
+  auto time_cfg_n = [&](const ftv_batch_cfg &cfg, uint32_t n, double *ms) -> int {
     c->cfg = cfg;
     int rc = batch_run(c, descs, ntasks, s);  // warm: capture + first touch
     if (rc) return rc;
     std::vector<float> t;
-    for (uint32_t i = 0; i < iters; ++i) {
+    for (uint32_t i = 0; i < n; ++i) {
       HIPCHK(hipEventRecord(e0, s));
       rc = batch_run(c, descs, ntasks, s);
       if (rc) return rc;
@@ -473,11 +475,14 @@ int ftv_tune_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void
       t.push_back(ms1);
     }
     std::sort(t.begin(), t.end());
-    *ms = t[t.size() / 2];
+    *ms = t[0];
     return FTV_OK;
   };
-  // coordinate descent from the default: one parameter at a time
-  ftv_batch_cfg cur = c->cfg;
+  auto time_cfg = [&](const ftv_batch_cfg &cfg, double *ms) { return time_cfg_n(cfg, iters, ms); };
+  // coordinate descent from the current schedule, one parameter at a time,
+  // two passes; then the winner is re-timed against the starting schedule
+  const ftv_batch_cfg start = c->cfg;
+  ftv_batch_cfg cur = start;
   double best_ms = 1e30;
   int rc = time_cfg(cur, &best_ms);
   const std::vector<uint32_t> tiles = {1024, 2048, 4096, 8192, 16384, 65536};
@@ -485,13 +490,14 @@ int ftv_tune_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void
   const std::vector<uint32_t> grids = {1, 2, 3, 4, 8};
   const std::vector<uint32_t> orders = {0, 1, 2};
   const std::vector<uint32_t> nts = {0, 1};
-  for (int field = 0; field < 5 && rc == FTV_OK; ++field) {
+  for (int field = 0; field < 10 && rc == FTV_OK; ++field) {
+    const int f5 = field % 5;
     const std::vector<uint32_t> &vals =
-        field == 0 ? tiles : field == 1 ? blocks : field == 2 ? grids : field == 3 ? orders : nts;
+        f5 == 0 ? tiles : f5 == 1 ? blocks : f5 == 2 ? grids : f5 == 3 ? orders : nts;
     for (uint32_t v : vals) {
       ftv_batch_cfg cand = cur;
-      uint32_t *f = field == 0 ? &cand.tile_vecs : field == 1 ? &cand.block
-                  : field == 2 ? &cand.grid_mult : field == 3 ? &cand.order : &cand.nt_stores;
+      uint32_t *f = f5 == 0 ? &cand.tile_vecs : f5 == 1 ? &cand.block
+                  : f5 == 2 ? &cand.grid_mult : f5 == 3 ? &cand.order : &cand.nt_stores;
       if (*f == v) continue;
       *f = v;
       double ms = 0;
@@ -502,6 +508,12 @@ int ftv_tune_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void
         cur = cand;
       }
     }
+  }
+  if (rc == FTV_OK && memcmp(&cur, &start, sizeof(cur)) != 0) {
+    double ms_cur = 0, ms_start = 0;
+    rc = time_cfg_n(cur, 2 * iters, &ms_cur);
+    if (rc == FTV_OK) rc = time_cfg_n(start, 2 * iters, &ms_start);
+    if (rc == FTV_OK && ms_start < ms_cur) cur = start;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -117,4 +117,13 @@ struct BlockVoteD {
 };
 hipError_t launch_vote_blocks(const BlockVoteD &b, int num_cus, hipStream_t s);
 
+// ---- sibling manager helpers (ftv_copy.hip) ------------------------------
+// Device-to-device copy of `bytes` (both pointers 16-byte aligned).
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, int num_cus, hipStream_t s);
+// Vote of m fingerprints per block (fps: m rows of nblocks): res[j] = 1 for a
+// sibling that differs from a strict majority in some block (u32 x m), then
+// the count of blocks without a strict majority (u64 at word (m+1)/2*2).
+hipError_t launch_fp_vote(const uint64_t *fps, uint32_t m, uint64_t nblocks, uint32_t *res, int num_cus,
+                          hipStream_t s);
+
 }  // namespace ftv

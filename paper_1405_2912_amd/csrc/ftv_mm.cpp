@@ -9,7 +9,9 @@
 // destroys the last good copy; a release with ok = 0 invalidates the sibling
 // the kernel used (Fig. 1).  ftv_mm_check validates the highest-version
 // siblings against each other by block fingerprints (the fingerprint kernel
-// of ftv_blocks.hip) and invalidates the minority.
+// of ftv_blocks.hip, then a per-block vote on the device) and invalidates the
+// minority.  Device-to-device copies use the streaming copy kernel of
+// ftv_copy.hip (the runtime's copy reached about half its rate on MI355X).
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -45,6 +47,7 @@ struct Area {
 
 struct ftv_mm {
   int device = -1;
+  int num_cus = 256;
   bool ft = false;
   std::mutex mu;
   std::vector<Area> areas;
@@ -53,9 +56,13 @@ struct ftv_mm {
   uint64_t staging_bytes = 0;
   uint64_t *d_fps = nullptr;
   uint64_t fps_cap = 0;
+  uint32_t *d_res = nullptr;   // vote result: flags per sibling + unresolved count
+  uint32_t *h_res = nullptr;   // pinned copy
 };
 
 namespace {
+
+constexpr size_t kResBytes = 4 * (FTV_MM_MAX_SIBLINGS + 2) + 8;
 
 uint64_t newest(const Area &a) {
   uint64_t v = 0;
@@ -105,9 +112,11 @@ int copy_sib(ftv_mm *mm, const Area &a, const Sib &src, Sib &dst, hipStream_t st
     return FTV_OK;
   }
   HIPCHK(hipSetDevice(mm->device));
-  hipMemcpyKind kind = src.memory == FTV_MEM_HOST ? hipMemcpyHostToDevice
-                       : dst.memory == FTV_MEM_HOST ? hipMemcpyDeviceToHost
-                                                    : hipMemcpyDeviceToDevice;
+  if (src.memory == FTV_MEM_DEVICE && dst.memory == FTV_MEM_DEVICE) {
+    HIPCHK(launch_copy(dst.ptr, src.ptr, a.bytes, mm->num_cus, stream));
+    return FTV_OK;
+  }
+  const hipMemcpyKind kind = src.memory == FTV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
   HIPCHK(hipMemcpyAsync(dst.ptr, src.ptr, a.bytes, kind, stream));
   if (dst.memory == FTV_MEM_HOST) HIPCHK(hipStreamSynchronize(stream));
   return FTV_OK;
@@ -179,6 +188,19 @@ int ftv_mm_create(int device, int fault_tolerant, ftv_mm **out) {
   if (!mm) return fail(FTV_E_NOMEM, "out of host memory");
   mm->device = device;
   mm->ft = fault_tolerant != 0;
+  if (device >= 0) {
+    int cus = 0;
+    const bool ok = hipSetDevice(device) == hipSuccess &&
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+                    hipMalloc((void **)&mm->d_res, kResBytes) == hipSuccess &&
+                    hipHostMalloc((void **)&mm->h_res, kResBytes) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      ftv_mm_destroy(mm);
+      return fail(FTV_E_NOMEM, "cannot allocate the manager's workspace");
+    }
+    if (cus > 0) mm->num_cus = cus;
+  }
   *out = mm;
   return FTV_OK;
 }
@@ -193,6 +215,8 @@ int ftv_mm_destroy(ftv_mm *mm) {
     for (Sib &s : a.sibs) free_sib(mm, s);
   if (mm->staging) (void)hipFree(mm->staging);
   if (mm->d_fps) (void)hipFree(mm->d_fps);
+  if (mm->d_res) (void)hipFree(mm->d_res);
+  if (mm->h_res) (void)hipHostFree(mm->h_res);
   delete mm;
   return FTV_OK;
 }
@@ -358,33 +382,15 @@ int ftv_mm_check(ftv_mm *mm, uint32_t area, uint64_t block_bytes, void *stream,
     }
     HIPCHK(launch_fingerprint(src, a->bytes, block_bytes, mm->d_fps + j * nblocks, s));
   }
-  std::vector<uint64_t> fps(m * nblocks);
-  HIPCHK(hipMemcpyAsync(fps.data(), mm->d_fps, 8 * m * nblocks, hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_fp_vote(mm->d_fps, (uint32_t)m, nblocks, mm->d_res, mm->num_cus, s));
+  const size_t res_words = (m + 1) / 2 * 2 + 2;
+  HIPCHK(hipMemcpyAsync(mm->h_res, mm->d_res, 4 * res_words, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  std::vector<char> bad(m, 0);
-  for (uint64_t b = 0; b < nblocks; ++b) {
-    uint64_t best = 0, best_support = 0;
-    bool differ = false;
-    for (uint64_t j = 0; j < m; ++j) {
-      const uint64_t f = fps[j * nblocks + b];
-      differ = differ || f != fps[b];
-      uint64_t support = 0;
-      for (uint64_t q = 0; q < m; ++q) support += fps[q * nblocks + b] == f;
-      if (support > best_support) {
-        best_support = support;
-        best = j;
-      }
-    }
-    if (2 * best_support > m) {
-      const uint64_t f = fps[best * nblocks + b];
-      for (uint64_t j = 0; j < m; ++j)
-        if (fps[j * nblocks + b] != f) bad[j] = 1;
-    } else if (differ) {
-      out->unresolved++;
-    }
-  }
+  uint64_t unresolved = 0;
+  memcpy(&unresolved, mm->h_res + (m + 1) / 2 * 2, 8);
+  out->unresolved = unresolved;
   for (uint64_t j = 0; j < m; ++j)
-    if (bad[j]) {
+    if (mm->h_res[j]) {
       a->sibs[cands[j]].valid = false;
       out->invalidated++;
     }
