@@ -105,6 +105,73 @@ def main_vote(ftv, ctx, steps, warmup, side):
             "alg_bytes": alg_bytes, "stats": s, "n": n}
 
 
+def bench_fp64_variant(ftv, ctx, steps=20, warmup=5, side=8192):
+    """The single-large-task workload's fp64 variant: k=3 8192x8192, 2 ULP."""
+    import torch
+    import synth.device as sd
+    n = side * side
+    log(f"bench: fp64 variant, k=3 {side}x{side}")
+    reps = sd.large_task_set(n, "f64")
+    cons = torch.empty_like(reps[0])
+    mask = torch.empty(n, dtype=torch.uint8, device=reps[0].device)
+    st = ftv.stats_tensor(reps[0].device)
+    tol = ftv.ulp(2)
+    for _ in range(warmup):
+        ftv.vote(ctx, reps, tol, cons, mask, st)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        ev[i][0].record()
+        ftv.vote(ctx, reps, tol, cons, mask, st)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    alg = 3 * n * 8 + n * 8 + n
+    verdict = ftv.read_stats(st)["verdict"]
+    del reps, cons, mask
+    torch.cuda.empty_cache()
+    return {"workload": f"k=3 replicas of a {side}x{side} fp64 matrix (512 MiB each), same faults, 2 ULP",
+            "ms": round(ms, 4), "replica_gbps": round(3 * n * 8 / ms / 1e6, 1),
+            "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4), "alg_bytes": alg, "verdict": verdict}
+
+
+def bench_small(ftv, ctx, sets=32, calls=256):
+    """The small parity workload (k=3 fp32, n=2^20) as a latency: one vote per
+    call, cycling through `sets` copies of the inputs so that consecutive calls
+    do not find theirs in the 256 MB last-level cache (MALL)."""
+    import torch
+    import synth
+    n = 1 << 20
+    r = synth.small_task_set()
+    base = [torch.from_numpy(x).cuda() for x in r]
+    reps = [[b.clone() for b in base] for _ in range(sets)]
+    outs = [(torch.empty(n, dtype=torch.float32, device="cuda"), torch.empty(n, dtype=torch.uint8, device="cuda"),
+             ftv.stats_tensor("cuda")) for _ in range(sets)]
+    tol = ftv.ulp(4)
+    for i in range(sets):
+        ftv.vote(ctx, reps[i], tol, *outs[i])
+    torch.cuda.synchronize()
+    # one call at a time: the events bracket the vote's two kernels and their
+    # launch on an idle device, i.e. the latency of one small vote
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for c in range(calls):
+        i = c % sets
+        ev[c][0].record()
+        ftv.vote(ctx, reps[i], tol, *outs[i])
+        ev[c][1].record()
+        ev[c][1].synchronize()
+    lat = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    us = lat[len(lat) // 2]
+    same = all(torch.equal(outs[i][0].view(torch.int32), outs[0][0].view(torch.int32)) for i in range(sets))
+    del reps, outs
+    torch.cuda.empty_cache()
+    return {"workload": f"k=3 fp32 n=2^20 (the parity workload), {sets} input copies cycled "
+                        f"({sets * 16} MiB, beyond the 256 MB MALL)",
+            "us_per_vote_median": round(us, 2), "us_p99": round(lat[int(0.99 * (len(lat) - 1))], 2),
+            "replica_gbps": round(3 * n * 4 / us / 1e3, 1),
+            "identical_across_copies": same}
+
+
 # ---------------------------------------------------------------------------
 # batched uneven tasks: one persistent launch vs one launch per task
 # ---------------------------------------------------------------------------
@@ -425,7 +492,7 @@ def main():
     ap.add_argument("--side", type=int, default=16384)
     ap.add_argument("--main-only", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=27)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
@@ -480,6 +547,8 @@ def main():
     del m
     torch.cuda.empty_cache()
     if not args.main_only:
+        out["fp64_variant"] = bench_fp64_variant(ftv, ctx)
+        out["small"] = bench_small(ftv, ctx)
         out["batched"] = bench_batched(ftv, ctx, args.batch_tasks)
         out["blocks"] = bench_blocks(ftv, ctx)
         out["siblings"] = bench_siblings(ftv)

@@ -6,14 +6,14 @@
 // are combined pairwise, level by level, a node being FNV-1a over the two words
 // (left, right).
 //
-// Whole blocks: one workgroup of T = min(256, BB/64) threads per block walks
+// Whole blocks: one workgroup of T = min(512, BB/64) threads per block walks
 // it in sub-chunks of 64*T bytes (one leaf per thread).  The sub-chunk is
 // read with fully coalesced 16-byte loads (chunk c*T + t to thread t, so each
 // load instruction of a wave covers 1 KiB of consecutive bytes), transposed
 // through LDS (double-buffered, XOR-swizzled so that neither the writes nor
 // the leaf-major reads conflict on banks) so that thread t then holds leaf t.
 // The first six tree levels are combined across the lanes of a wave, the next
-// (up to two) over the wave roots in LDS, the last (up to two) over the
+// (up to three) over the wave roots in LDS, the last (up to two) over the
 // sub-chunk roots.  The loads of the next sub-chunk are in flight while the
 // current one is hashed.  Reading each lane's own 64-byte leaf directly from
 // HBM instead (lanes 64 bytes apart in every load) measured 1.6x slower.
@@ -132,8 +132,14 @@ __device__ __forceinline__ const void *rep_ptr(const BlockVoteD &b, int r) {
 }
 
 // ---- whole blocks: coalesced loads transposed through LDS -----------------
-constexpr uint32_t kMaxT = 256;         // threads per block workgroup
-constexpr uint32_t kSubChunks = 4 * kMaxT;  // 16-byte chunks per sub-chunk (max)
+// Threads per whole-block workgroup.  The block vote (k reads, a consensus
+// and a mask write) is fastest with 512 (a 32 KiB sub-chunk per step, its LDS
+// tile double-buffered in 64 KiB, two workgroups per CU): 2.58 ms for the
+// k = 5 fp64 16384^2 checkpoint against 2.66 ms with 256 and 2.72 ms with
+// 1024.  The read-only fingerprint pass is fastest with 256 (0.33 ms for a
+// 2 GiB buffer against 0.40 ms with 512).
+constexpr uint32_t kVoteT = 512;
+constexpr uint32_t kFingerprintT = 256;
 
 // LDS slot of 16-byte chunk g of a sub-chunk.  Thread t writes chunks c*T + t
 // and reads chunks 4t .. 4t+3; XOR-ing bits 0-1 with bits 4-5 makes every
@@ -194,8 +200,8 @@ __device__ __forceinline__ void hash_step(const BlockVoteD &b, const Walk &w, ui
 // Sub-chunk roots of block `blk` in the first K buffers of b (K = 1:
 // fingerprints of b.rep[0]), the next step's loads in flight while one is
 // hashed.  Ends with a barrier: sroot is then complete.
-template <int K, bool CONS>
-__device__ __forceinline__ void walk_block(const BlockVoteD &b, const Walk &w, u32x4 (*lbuf)[kSubChunks],
+template <int K, bool CONS, uint32_t T>
+__device__ __forceinline__ void walk_block(const BlockVoteD &b, const Walk &w, u32x4 (*lbuf)[4 * T],
                                            uint64_t *sw, uint64_t (*sroot)[4]) {
   const uint32_t nstep = (uint32_t)K << w.lg_nsub;
   u32x4 va[4], vb[4];
@@ -220,12 +226,12 @@ __device__ __forceinline__ Walk make_walk(uint64_t blk, uint64_t block_bytes) {
   return w;
 }
 
-__global__ __launch_bounds__(kMaxT) void k_fingerprint(BlockVoteD b) {
-  __shared__ u32x4 lbuf[2][kSubChunks];
-  __shared__ uint64_t sw[4];
+__global__ __launch_bounds__(kFingerprintT) void k_fingerprint(BlockVoteD b) {
+  __shared__ u32x4 lbuf[2][4 * kFingerprintT];
+  __shared__ uint64_t sw[kFingerprintT / 64];
   __shared__ uint64_t sroot[1][4];
   const Walk w = make_walk(blockIdx.x, b.block_bytes);
-  walk_block<1, false>(b, w, lbuf, sw, sroot);
+  walk_block<1, false, kFingerprintT>(b, w, lbuf, sw, sroot);
   if (threadIdx.x == 0) b.fps[blockIdx.x] = lds_tree(sroot[0], w.nsub);
 }
 
@@ -264,13 +270,13 @@ __device__ __forceinline__ uint32_t vote_fps(const uint64_t (&f)[K], int *src_ou
 // replica.  Blocks without a majority are left to pass 2, which rewrites their
 // consensus and mask.
 template <int K>
-__global__ __launch_bounds__(kMaxT) void k_vote_blocks(BlockVoteD b) {
-  __shared__ u32x4 lbuf[2][kSubChunks];
-  __shared__ uint64_t sw[4];
+__global__ __launch_bounds__(kVoteT) void k_vote_blocks(BlockVoteD b) {
+  __shared__ u32x4 lbuf[2][4 * kVoteT];
+  __shared__ uint64_t sw[kVoteT / 64];
   __shared__ uint64_t sroot[K][4];
   const uint64_t blk = blockIdx.x;
   const Walk w = make_walk(blk, b.block_bytes);
-  walk_block<K, true>(b, w, lbuf, sw, sroot);
+  walk_block<K, true, kVoteT>(b, w, lbuf, sw, sroot);
   if (threadIdx.x < (uint32_t)K) {
     const uint32_t r = threadIdx.x;
     const uint64_t f = lds_tree(sroot[r], w.nsub);
@@ -512,16 +518,16 @@ hipError_t launch_scan(const BlockVoteD &b, int num_cus, hipStream_t s) {
 }
 
 // Threads of a whole-block workgroup: one leaf per thread per sub-chunk.
-inline uint32_t block_threads(uint64_t block_bytes) {
+inline uint32_t block_threads(uint64_t block_bytes, uint32_t max_t) {
   const uint64_t leaves = block_bytes / 64;
-  return (uint32_t)(leaves < kMaxT ? leaves : kMaxT);
+  return (uint32_t)(leaves < max_t ? leaves : max_t);
 }
 
 template <int K>
 hipError_t launch_blocks_hash(const BlockVoteD &b, hipStream_t s) {
   const uint64_t nwhole = b.nbytes / b.block_bytes;
   if (nwhole) {
-    hipLaunchKernelGGL((k_vote_blocks<K>), dim3((uint32_t)nwhole), dim3(block_threads(b.block_bytes)), 0, s, b);
+    hipLaunchKernelGGL((k_vote_blocks<K>), dim3((uint32_t)nwhole), dim3(block_threads(b.block_bytes, kVoteT)), 0, s, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -566,7 +572,7 @@ hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_b
     b.block_bytes = block_bytes;
     b.nblocks = nblocks;
     b.fps = fp_out;
-    hipLaunchKernelGGL(k_fingerprint, dim3((uint32_t)nwhole), dim3(block_threads(block_bytes)), 0, s, b);
+    hipLaunchKernelGGL(k_fingerprint, dim3((uint32_t)nwhole), dim3(block_threads(block_bytes, kFingerprintT)), 0, s, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
