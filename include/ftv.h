@@ -160,7 +160,10 @@ typedef struct ftv_batch_cfg {
   uint32_t grid_mult;  /* workgroups per compute unit */
   uint32_t order;      /* tiles are handed out task by task in this order:
                           0 = as given, 1 = largest task first (LPT),
-                          2 = smallest task first */
+                          2 = smallest task first, 3 = grouped by value
+                          type, tolerance and k, largest first within a
+                          group (co-resident workgroups then run the same
+                          code) */
   uint32_t nt_stores;  /* 1 = non-temporal stores for consensus and mask */
   uint32_t reserved;
 } ftv_batch_cfg;

@@ -133,7 +133,7 @@ int cfg_check(const ftv_batch_cfg &c) {
   if (c.block != 256 && c.block != 512) return fail(FTV_E_INVALID, "block must be 256 or 512");
   if (c.tile_vecs < 256 || c.tile_vecs > (1u << 22)) return fail(FTV_E_INVALID, "tile_vecs out of range");
   if (c.grid_mult < 1 || c.grid_mult > 32) return fail(FTV_E_INVALID, "grid_mult out of range");
-  if (c.order > 2 || c.nt_stores > 1 || c.reserved != 0) return fail(FTV_E_INVALID, "bad order/nt_stores");
+  if (c.order > 3 || c.nt_stores > 1 || c.reserved != 0) return fail(FTV_E_INVALID, "bad order/nt_stores");
   return FTV_OK;
 }
 
@@ -249,6 +249,11 @@ int build_tables(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStr
     std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return bytes_of(a) > bytes_of(b); });
   else if (c->cfg.order == 2)
     std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return bytes_of(a) < bytes_of(b); });
+  else if (c->cfg.order == 3)
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+      if (tasks[a].spec != tasks[b].spec) return tasks[a].spec < tasks[b].spec;
+      return bytes_of(a) > bytes_of(b);
+    });
   uint64_t *hdr = reinterpret_cast<uint64_t *>(c->h_tab);
   uint64_t *pre = reinterpret_cast<uint64_t *>(c->h_tab + prefix_off());
   TaskD *ht = reinterpret_cast<TaskD *>(c->h_tab + tasks_off(c->cap_tasks));
@@ -488,7 +493,7 @@ int ftv_tune_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void
   const std::vector<uint32_t> tiles = {1024, 2048, 4096, 8192, 16384, 65536};
   const std::vector<uint32_t> blocks = {256, 512};
   const std::vector<uint32_t> grids = {1, 2, 3, 4, 8};
-  const std::vector<uint32_t> orders = {0, 1, 2};
+  const std::vector<uint32_t> orders = {0, 1, 2, 3};
   const std::vector<uint32_t> nts = {0, 1};
   for (int field = 0; field < 10 && rc == FTV_OK; ++field) {
     const int f5 = field % 5;

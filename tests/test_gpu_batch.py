@@ -109,7 +109,7 @@ def test_every_schedule_gives_identical_results(gpu, ctx):
     for tv in (256, 1024, 4096, 65536):
         for block in (256, 512):
             for gm in (1, 3, 8):
-                for order in (0, 1, 2):
+                for order in (0, 1, 2, 3):
                     cfg = gpu.BatchCfg(tv, block, gm, order, (tv + order) % 2, 0)
                     print(f"case: schedule tile={tv} block={block} grid={gm} order={order}", flush=True)
                     ctx.set_batch_config(cfg)
