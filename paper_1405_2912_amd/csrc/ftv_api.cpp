@@ -490,7 +490,7 @@ int ftv_tune_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void
   ftv_batch_cfg cur = start;
   double best_ms = 1e30;
   int rc = time_cfg(cur, &best_ms);
-  const std::vector<uint32_t> tiles = {1024, 2048, 4096, 8192, 16384, 65536};
+  const std::vector<uint32_t> tiles = {1024, 4096, 16384, 65536, 131072, 262144};
   const std::vector<uint32_t> blocks = {256, 512};
   const std::vector<uint32_t> grids = {1, 2, 3, 4, 8};
   const std::vector<uint32_t> orders = {0, 1, 2, 3};

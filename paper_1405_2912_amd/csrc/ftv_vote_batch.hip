@@ -48,19 +48,30 @@ __global__ __launch_bounds__(512) void k_vote_batch(BatchLaunch b) {
   __shared__ TileD s_tl;
   const uint64_t ntiles = b.ntiles_dev[0];
   const uint64_t ntasks = b.ntiles_dev[1];
+  uint64_t hint = 0;  // thread 0: task of the previous tile (tile numbers only grow)
   for (;;) {
     if (threadIdx.x == 0) {
       const uint32_t q = __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_tile = q;
       if (q < ntiles) {
         if (b.prefix) {
-          // the task whose tile range holds q: last t with prefix[t] <= q
-          uint64_t lo = 0, hi = ntasks;
+          // the task whose tile range holds q: the last t with prefix[t] <= q.
+          // It is at or after `hint`; gallop from there (usually one probe:
+          // the same or the next task), then bisect, keeping
+          // prefix[lo] <= q < prefix[hi] (prefix[ntasks] = ntiles > q).
+          uint64_t lo = hint, hi = hint + 1, step = 1;
+          while (hi < ntasks && b.prefix[hi] <= q) {
+            lo = hi;
+            step <<= 1;
+            hi = lo + step;
+          }
+          if (hi > ntasks) hi = ntasks;
           while (hi - lo > 1) {
             const uint64_t mid = (lo + hi) >> 1;
             if (b.prefix[mid] <= q) lo = mid;
             else hi = mid;
           }
+          hint = lo;
           const uint64_t j = q - b.prefix[lo];
           const uint64_t nvec = b.tasks[lo].nvec;
           TileD tl;
