@@ -427,6 +427,65 @@ int ftv_mm_siblings(ftv_mm *mm, uint32_t area, ftv_sibling_info *out, uint32_t c
 int ftv_mm_check(ftv_mm *mm, uint32_t area, uint64_t block_bytes, void *stream,
                  ftv_mm_check_result *out);
 
+/* ---- redundant execution with light-weight fault tolerance (Sec. IV-C, IV-D) *
+ * A task has several implementations, each a kernel of some processing unit
+ * with a profile in `units` (ftv_unit: runtime in SECONDS here, valid runs,
+ * runs).  An attempt runs the task on the k implementations with the lowest
+ * fault-aware runtime (ties: lower index) not yet failed in this call, each
+ * into a replica buffer of the library on a stream of its own.  A run that
+ * reports a direct fault (its run function returns non-zero, or a HIP error
+ * is pending after it) or, for a unit with a profile (runtime > 0 and
+ * valid > 0), does not finish within runtime x timeout_factor seconds is
+ * abandoned: not voted, counted as a run that was not valid (total + 1), its
+ * implementation excluded for the rest of the call, and its buffer reused only
+ * after its work has drained (the call does not wait for it).  At least two
+ * surviving runs are voted with ftv_vote into `out`; each voted run counts
+ * (total + 1) and is valid (valid + 1) when it agrees with the consensus
+ * everywhere, and the runtime of a valid run's unit becomes the running mean
+ * of its valid runs' GPU times.  An UNRESOLVED vote changes no profile and
+ * starts the next attempt, re-ranked; fewer than two implementations left
+ * end the call.  Readings: the paper restarts with "the next best
+ * combination" after a fault and votes DMR pairs; the exclusion rule, the
+ * running mean and counting a failed run as an invalid one are this
+ * library's. */
+typedef int (*ftv_task_fn)(void *user, void *out, void *stream);
+
+typedef struct ftv_impl {
+  ftv_task_fn run;   /* enqueue the task's result (n elements) into the device
+                        buffer `out` on `stream` (a hipStream_t); must return
+                        without waiting for the work */
+  void *user;        /* passed to run */
+  uint32_t unit;     /* index of its profile in `units` */
+  uint32_t reserved;
+} ftv_impl;
+
+typedef struct ftv_redundancy_cfg {
+  uint32_t k;              /* runs per attempt: 2 (DMR) .. FTV_MAX_K */
+  uint32_t max_attempts;   /* >= 1 */
+  double timeout_factor;   /* deadline = profiled runtime x factor; 0 = none */
+  int32_t dtype;           /* FTV_F32 .. FTV_I64 */
+  uint32_t reserved;       /* 0 */
+  ftv_tol tol;             /* the vote's tolerance */
+} ftv_redundancy_cfg;
+
+typedef struct ftv_redundancy_report {
+  uint32_t attempts;       /* attempts started */
+  int32_t verdict;         /* of the last vote; FTV_UNRESOLVED if none resolved */
+  uint32_t timeouts;       /* runs abandoned at their deadline */
+  uint32_t errors;         /* runs that reported a direct fault */
+  uint32_t winner_unit;    /* unit of the vote's winner (resolved votes) */
+  uint32_t reserved;
+  double seconds;          /* wall time of the call */
+} ftv_redundancy_report;
+
+/* `impls` (nimpl >= 2) and `units` are HOST arrays; `units` is updated in
+ * place.  `out` (device, n elements of cfg->dtype) receives the consensus of
+ * the last vote.  Returns FTV_OK also when no vote resolved (see
+ * rep->verdict); FTV_E_INVALID / FTV_E_K / FTV_E_DTYPE on bad arguments,
+ * FTV_E_NOMEM, FTV_E_HIP.  Not thread-safe per context. */
+int ftv_run_redundant(ftv_ctx *ctx, const ftv_impl *impls, uint32_t nimpl, ftv_unit *units, uint32_t nunits,
+                      const ftv_redundancy_cfg *cfg, uint64_t n, void *out, ftv_redundancy_report *rep);
+
 #ifdef __cplusplus
 }
 #endif

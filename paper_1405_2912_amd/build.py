@@ -18,7 +18,8 @@ OBJ = os.path.join(ROOT, "_build", "ftv")
 LIB = os.path.join(PKG, "libftv.so")
 
 SOURCES = ["ftv_vote_f32.hip", "ftv_vote_f64.hip", "ftv_vote_i32.hip", "ftv_vote_i64.hip", "ftv_vote_batch.hip",
-           "ftv_blocks.hip", "ftv_copy.hip", "ftv_api.cpp", "ftv_server.cpp", "ftv_units.cpp", "ftv_mm.cpp"]
+           "ftv_blocks.hip", "ftv_copy.hip", "ftv_api.cpp", "ftv_server.cpp", "ftv_units.cpp", "ftv_mm.cpp",
+           "ftv_run.cpp"]
 
 ARCH = "gfx950"
 # -ffp-contract=off and no flush-to-zero: the relative tolerance test must be

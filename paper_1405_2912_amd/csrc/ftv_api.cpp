@@ -123,6 +123,9 @@ struct ftv_ctx {
   ftv_batch_cfg g_cfg{};
   // block vote workspace
   uint64_t *blk_acc = nullptr;
+  // ftv_run_redundant: replicas abandoned after a timeout, freed once their
+  // work has finished (ftv_run.cpp)
+  RunState *run = nullptr;
 };
 
 namespace {
@@ -397,11 +400,20 @@ int ftv_ctx_create(int device, ftv_ctx **out) {
   return FTV_OK;
 }
 
+}  // extern "C"
+
+namespace ftv {
+RunState *&ctx_run_state(ftv_ctx *c) { return c->run; }
+}  // namespace ftv
+
+extern "C" {
+
 int ftv_ctx_destroy(ftv_ctx *c) {
   if (!c) return FTV_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   free_batch(c);
+  run_state_destroy(c->run);
   if (c->partials) (void)hipFree(c->partials);
   if (c->d_queue) (void)hipFree(c->d_queue);
   if (c->blk_acc) (void)hipFree(c->blk_acc);

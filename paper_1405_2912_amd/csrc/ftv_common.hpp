@@ -24,6 +24,12 @@ TolD to_tol_d(int dtype, const ftv_tol &t);
 // alignment rules.
 int make_task(const ftv_vote_desc *d, bool strict, TaskD *out);
 
+// State of ftv_run_redundant kept in a context (abandoned replicas); freed
+// with the context after the device has been synchronised.
+struct RunState;
+void run_state_destroy(RunState *r);
+RunState *&ctx_run_state(ftv_ctx *c);
+
 }  // namespace ftv
 
 #define HIPCHK(call)                                   \

@@ -99,6 +99,24 @@ class SiblingInfo(Structure):
                 ("reserved", c_uint32)]
 
 
+TaskFn = ctypes.CFUNCTYPE(c_int, c_void_p, c_void_p, c_void_p)
+
+
+class Impl(Structure):
+    _fields_ = [("run", TaskFn), ("user", c_void_p), ("unit", c_uint32), ("reserved", c_uint32)]
+
+
+class RedundancyCfg(Structure):
+    _fields_ = [("k", c_uint32), ("max_attempts", c_uint32), ("timeout_factor", c_double),
+                ("dtype", c_int32), ("reserved", c_uint32), ("tol", Tol)]
+
+
+class RedundancyReport(Structure):
+    _fields_ = [("attempts", c_uint32), ("verdict", c_int32), ("timeouts", c_uint32),
+                ("errors", c_uint32), ("winner_unit", c_uint32), ("reserved", c_uint32),
+                ("seconds", c_double)]
+
+
 class MMCheckResult(Structure):
     _fields_ = [("checked", c_uint32), ("invalidated", c_uint32), ("unresolved", c_uint64),
                 ("blocks", c_uint64)]
@@ -110,7 +128,7 @@ EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv
            "ftv_submit", "ftv_poll", "ftv_release", "ftv_server_get_stats",
            "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote",
            "ftv_mm_create", "ftv_mm_destroy", "ftv_mm_register", "ftv_mm_request", "ftv_mm_release",
-           "ftv_mm_siblings", "ftv_mm_check"]
+           "ftv_mm_siblings", "ftv_mm_check", "ftv_run_redundant"]
 
 _lib = None
 
@@ -155,6 +173,8 @@ def load():
     L.ftv_mm_release.argtypes = [vp, c_uint32, c_uint32, c_int]
     L.ftv_mm_siblings.argtypes = [vp, c_uint32, POINTER(SiblingInfo), c_uint32, POINTER(c_uint32)]
     L.ftv_mm_check.argtypes = [vp, c_uint32, c_uint64, vp, POINTER(MMCheckResult)]
+    L.ftv_run_redundant.argtypes = [vp, POINTER(Impl), c_uint32, POINTER(Unit), c_uint32,
+                                    POINTER(RedundancyCfg), c_uint64, vp, POINTER(RedundancyReport)]
     for name in EXPORTS:
         fn = getattr(L, name, None)
         if fn is not None and name not in ("ftv_version", "ftv_last_error", "ftv_now_ns",
@@ -516,3 +536,31 @@ class MemoryManager:
             self.close()
         except Exception:
             pass
+
+
+# ---- redundant execution with timeouts and retries ----------------------------
+def run_redundant(ctx: Context, impls, units, out, tol: Tol, k: int = 2, max_attempts: int = 3,
+                  timeout_factor: float = 0.0) -> dict:
+    """impls: list of (fn, unit) where fn(out_ptr: int, stream_ptr: int) -> int
+    enqueues the task into the device buffer at out_ptr on the HIP stream
+    stream_ptr and returns 0 (non-zero: a direct fault).  units: a ctypes array
+    of Unit (updated in place).  out: the device tensor for the consensus."""
+    keep = []
+
+    def wrap(fn):
+        def cb(_user, out_ptr, stream_ptr):
+            try:
+                return int(fn(int(out_ptr or 0), int(stream_ptr or 0)))
+            except Exception:
+                return -1
+        c = TaskFn(cb)
+        keep.append(c)
+        return c
+    arr = (Impl * len(impls))(*[Impl(wrap(fn), None, int(u), 0) for fn, u in impls])
+    cfg = RedundancyCfg(int(k), int(max_attempts), float(timeout_factor), dtype_code(out), 0, tol)
+    rep = RedundancyReport()
+    _check(load().ftv_run_redundant(ctx.handle, arr, len(impls), units, len(units),
+                                    ctypes.byref(cfg), out.numel(), c_void_p(out.data_ptr()),
+                                    ctypes.byref(rep)))
+    return {"attempts": int(rep.attempts), "verdict": int(rep.verdict), "timeouts": int(rep.timeouts),
+            "errors": int(rep.errors), "winner_unit": int(rep.winner_unit), "seconds": float(rep.seconds)}

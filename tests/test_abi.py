@@ -51,13 +51,15 @@ def _c_sizes():
 #include <stdio.h>
 #include "ftv.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ftv_tol), sizeof(ftv_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ftv_tol), sizeof(ftv_stats),
          sizeof(ftv_vote_desc), sizeof(ftv_batch_cfg), sizeof(ftv_block_stats),
          sizeof(ftv_server_cfg), sizeof(ftv_request), sizeof(ftv_result), sizeof(ftv_server_stats),
-         sizeof(ftv_sibling_info), sizeof(ftv_mm_check_result));
-  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(ftv_stats, verdict), offsetof(ftv_vote_desc, tol),
+         sizeof(ftv_sibling_info), sizeof(ftv_mm_check_result), sizeof(ftv_impl),
+         sizeof(ftv_redundancy_cfg), sizeof(ftv_redundancy_report));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(ftv_stats, verdict), offsetof(ftv_vote_desc, tol),
          offsetof(ftv_vote_desc, stats), offsetof(ftv_request, t_arrival_ns),
-         offsetof(ftv_sibling_info, readers), offsetof(ftv_mm_check_result, blocks));
+         offsetof(ftv_sibling_info, readers), offsetof(ftv_mm_check_result, blocks),
+         offsetof(ftv_redundancy_cfg, tol), offsetof(ftv_redundancy_report, seconds));
   return 0;
 }
 '''
@@ -76,11 +78,13 @@ def test_ctypes_layout_matches_c():
     sizes, offs = _c_sizes()
     mine = [ctypes.sizeof(t) for t in (b.Tol, b.Stats, b.VoteDesc, b.BatchCfg, b.BlockStats,
                                        b.ServerCfg, b.Request, b.Result, b.ServerStats,
-                                       b.SiblingInfo, b.MMCheckResult)]
+                                       b.SiblingInfo, b.MMCheckResult, b.Impl, b.RedundancyCfg,
+                                       b.RedundancyReport)]
     assert mine == sizes
     assert [b.Stats.verdict.offset, b.VoteDesc.tol.offset, b.VoteDesc.stats.offset,
             b.Request.t_arrival_ns.offset, b.SiblingInfo.readers.offset,
-            b.MMCheckResult.blocks.offset] == offs
+            b.MMCheckResult.blocks.offset, b.RedundancyCfg.tol.offset,
+            b.RedundancyReport.seconds.offset] == offs
 
 
 def test_host_validation_without_gpu(lib):
