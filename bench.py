@@ -426,6 +426,50 @@ def bench_siblings(ftv, gib: int = 2):
 
 
 # ---------------------------------------------------------------------------
+# redundant execution (DMR) of the single large task, with deadlines
+# ---------------------------------------------------------------------------
+def bench_redundant(ftv, ctx, side=16384, calls=7):
+    """Three implementations of the 1 GiB fp32 task (stand-ins: each copies one
+    of the large task's replicas into its output), DMR on the two with the
+    lowest fault-aware runtime, deadline 10x the profile, then the vote."""
+    import ctypes
+    import torch
+    import synth.device as sd
+    n = side * side
+    log("bench: redundant execution (DMR) of the large task")
+    reps = sd.large_task_set(n, "f32")
+    hip = ctypes.CDLL("libamdhip64.so")
+
+    def impl(src):
+        def run(out_ptr, stream_ptr):
+            return hip.hipMemcpyAsync(ctypes.c_void_p(out_ptr), ctypes.c_void_p(src.data_ptr()),
+                                      ctypes.c_size_t(n * 4), 3, ctypes.c_void_p(stream_ptr))
+        return run
+    units = (ftv.Unit * 3)(ftv.Unit(1e-3, 0, 0), ftv.Unit(1e-3, 0, 0), ftv.Unit(1e-3, 0, 0))
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    impls = [(impl(reps[i]), i) for i in range(3)]
+    times, last = [], None
+    for _ in range(calls):
+        torch.cuda.synchronize()
+        last = ftv.run_redundant(ctx, impls, units, out, ftv.ulp(4), k=2, max_attempts=2, timeout_factor=10.0)
+        times.append(last["seconds"] * 1e3)
+    ms = sorted(times)[len(times) // 2]
+    # every element of the consensus is one of the two voted runs' values
+    ok = bool(((out.view(torch.int32) == reps[0].view(torch.int32)) |
+               (out.view(torch.int32) == reps[1].view(torch.int32))).all())
+    alg = 2 * 2 * n * 4 + (2 * n * 4 + n * 4 + n)    # two runs' copies, then the k=2 vote
+    del reps, out
+    torch.cuda.empty_cache()
+    return {"workload": f"DMR of the k=3 fp32 {side}x{side} task's stand-in kernels (each copies one "
+                        f"replica), 3 implementations, deadline 10x profile, ULP 4 vote",
+            "ms_per_task": round(ms, 3), "attempts": last["attempts"], "verdict": last["verdict"],
+            "timeouts": last["timeouts"], "errors": last["errors"],
+            "gpu_bytes": alg, "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "consensus_from_voted_runs": ok,
+            "profiles_after": [[round(u.runtime * 1e3, 3), int(u.valid), int(u.total)] for u in units]}
+
+
+# ---------------------------------------------------------------------------
 # serving: Poisson arrivals, continuous batching, p50/p99 latency
 # ---------------------------------------------------------------------------
 def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0):
@@ -552,6 +596,7 @@ def main():
         out["batched"] = bench_batched(ftv, ctx, args.batch_tasks)
         out["blocks"] = bench_blocks(ftv, ctx)
         out["siblings"] = bench_siblings(ftv)
+        out["redundant"] = bench_redundant(ftv, ctx)
         out["serving"] = bench_serving(ftv, ctx, args.serve_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
