@@ -209,6 +209,7 @@ int ensure_graph(ftv_ctx *c, uint32_t grid) {
   hipError_t e2f = launch_batch_finalize(b, c->cap_stream);
   hipGraph_t g{};
   hipError_t e3 = hipStreamEndCapture(c->cap_stream, &g);
+  if (e3 == hipSuccess && (e1 != hipSuccess || e2 != hipSuccess || e2f != hipSuccess)) (void)hipGraphDestroy(g);
   if (e1 != hipSuccess) return hip_fail(e1, "capture zero kernel");
   if (e2 != hipSuccess) return hip_fail(e2, "capture batch kernel");
   if (e2f != hipSuccess) return hip_fail(e2f, "capture finalize kernel");
