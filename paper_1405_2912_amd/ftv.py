@@ -141,6 +141,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1405_2912_amd.build` (there is no CPU fallback)")
+    # PyTorch supplies the device memory and streams; it is imported before the
+    # library makes its first HIP call (importing it afterwards left torch
+    # seeing no GPU on MI355X).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp = c_void_p
     L.ftv_version.restype = c_char_p
