@@ -543,6 +543,8 @@ def main():
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
+    ap.add_argument("--only", choices=["batched", "blocks"],
+                    help="run only this workload and print its result (for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the voter's multi-GPU "
@@ -560,6 +562,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only:
+        run = {"batched": lambda: bench_batched(ftv, ctx, args.batch_tasks),
+               "blocks": lambda: bench_blocks(ftv, ctx)}[args.only]
+        res = run()
+        ctx.close()
+        print(json.dumps({args.only: res}), flush=True)
+        return
     m = main_vote(ftv, ctx, args.steps, args.warmup, args.side)
     ms_per_step = m["wall"] / args.steps * 1e3
     value = m["replica_bytes"] / (ms_per_step / 1e3) / 1e9
