@@ -174,15 +174,17 @@ __device__ __forceinline__ void hash_step(const BlockVoteD &b, const Walk &w, ui
   const uint32_t r = s >> w.lg_nsub, sub = s & (w.nsub - 1);
   const uint64_t soff = w.boff + (uint64_t)sub * w.sub_bytes;
   if (CONS && r == 0) {
-    uint8_t *cb = reinterpret_cast<uint8_t *>(b.cons) + soff + 16ull * t;
+    const uintptr_t cb = reinterpret_cast<uintptr_t>(b.cons) + soff;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) st16(cb, (uint64_t)c * w.nth, v[c], true);
+    for (int c = 0; c < 4; ++c) stream_store16(cb, (c * w.nth + t) * 16u, v[c]);
     if (b.mask) {
       // 64 bytes of the sub-chunk per thread = 8 (8-byte) or 16 (4-byte) elements
       const uint32_t es = b.dtype == FTV_F32 || b.dtype == FTV_I32 ? 4u : 8u;
       const uint32_t per = 64u / es;
-      uint32_t *mw = reinterpret_cast<uint32_t *>(b.mask + soff / es + (uint64_t)t * per);
-      for (uint32_t q = 0; q < per / 4; ++q) st_nt(mw + q, 0u, true);
+      // one store per thread, so that each store instruction covers whole lines
+      const uintptr_t mb = reinterpret_cast<uintptr_t>(b.mask) + soff / es;
+      if (per == 16) stream_store16(mb, t * 16u, u32x4{0u, 0u, 0u, 0u});
+      else stream_store8(mb, t * 8u, 0ull);
     }
   }
 #pragma unroll
@@ -292,9 +294,9 @@ __global__ __launch_bounds__(kVoteT) void k_vote_blocks(BlockVoteD b) {
   if (!(bm & 0x80u) && (bm & 1u)) {  // replica 0 is not the majority: recopy
     const u32x4 *sp = reinterpret_cast<const u32x4 *>(
         reinterpret_cast<const uint8_t *>(rep_ptr<K>(b, src)) + w.boff);
-    u32x4 *dp = reinterpret_cast<u32x4 *>(reinterpret_cast<uint8_t *>(b.cons) + w.boff);
+    const uintptr_t dp = reinterpret_cast<uintptr_t>(b.cons) + w.boff;
     for (uint32_t i = threadIdx.x; i < (uint32_t)(b.block_bytes / 16); i += w.nth)
-      st16(dp, i, ld16(sp, i), true);
+      stream_store16(dp, i * 16u, ld16(sp, i));
   }
   if (threadIdx.x == 0) b.blockmap[blk] = (uint8_t)bm;
 }

@@ -20,6 +20,14 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCopyUnroll = 4;
 
+// Stores go out non-temporal at agent scope (nt sc1), written through the
+// XCD's L2, against a buffer resource based at the step's first vector.
+__device__ __forceinline__ void copy_store16(uintptr_t base, uint32_t off, u32x4 v) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(base), (short)0, 0x7fffffff, 0x00020000);
+  __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 2 | 16);
+}
+
 __global__ __launch_bounds__(256) void k_copy(u32x4 *dst, const u32x4 *src, uint64_t nvec,
                                               uint8_t *dst_tail, const uint8_t *src_tail, uint32_t ntail) {
   const uint64_t step = (uint64_t)blockDim.x * kCopyUnroll;
@@ -29,9 +37,9 @@ __global__ __launch_bounds__(256) void k_copy(u32x4 *dst, const u32x4 *src, uint
 #pragma unroll
     for (int u = 0; u < kCopyUnroll; ++u)
       v[u] = __builtin_nontemporal_load(src + base + (uint64_t)u * blockDim.x + threadIdx.x);
+    const uintptr_t db = reinterpret_cast<uintptr_t>(dst + base);
 #pragma unroll
-    for (int u = 0; u < kCopyUnroll; ++u)
-      __builtin_nontemporal_store(v[u], dst + base + (uint64_t)u * blockDim.x + threadIdx.x);
+    for (int u = 0; u < kCopyUnroll; ++u) copy_store16(db, (u * blockDim.x + threadIdx.x) * 16u, v[u]);
   }
   if (base < nvec) {  // this workgroup's partial step
     for (uint64_t i = base + threadIdx.x; i < nvec; i += blockDim.x) dst[i] = src[i];

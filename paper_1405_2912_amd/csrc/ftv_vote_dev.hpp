@@ -461,6 +461,28 @@ __device__ __forceinline__ void st_nt(T *p, T v, bool nt) {
   else *p = v;
 }
 
+// Streaming output stores of the vector path: non-temporal at agent scope
+// (nt sc1), so that the consensus and mask vectors, written once and never
+// read back by the kernel, are written through the XCD's L2 instead of being
+// written back later while the replica reads are streaming.  They are buffer
+// stores against a resource based at the step's first vector, so the 32-bit
+// offset covers any task size.
+constexpr int kStreamStorePolicy = 2 | 16;  // nt | sc1
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(uintptr_t base) {
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(base), (short)0, 0x7fffffff,
+                                           0x00020000);
+}
+// One streaming store at byte offset `off` from a workgroup-uniform base.
+__device__ __forceinline__ void stream_store16(uintptr_t base, uint32_t off, u32x4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, stream_rsrc(base), off, 0, kStreamStorePolicy);
+}
+__device__ __forceinline__ void stream_store8(uintptr_t base, uint32_t off, uint64_t v) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 w = {(uint32_t)v, (uint32_t)(v >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b64(w, stream_rsrc(base), off, 0, kStreamStorePolicy);
+}
+
 // Vote vectors [v0, v1) of a task with the calling workgroup (vector path:
 // vector = 16 bytes; scalar path: vector = one element).  Lane `tid` handles
 // v0 + tid + u*nthreads for u < U in each step, all loads of a step issued
@@ -507,6 +529,8 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
     // fast pass: every element is voted and stored; elements whose replicas
     // hold two or more differing bit patterns are flagged in `need`
     uint32_t need = 0;
+    const __amdgpu_buffer_rsrc_t rc = stream_rsrc(reinterpret_cast<uintptr_t>(t.cons) + base * 16u);
+    const __amdgpu_buffer_rsrc_t rm = stream_rsrc(reinterpret_cast<uintptr_t>(t.mask) + base * V);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t vi = base + (uint64_t)u * nth + tid;
@@ -530,10 +554,19 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
       }
       if (valid) {
         if constexpr (VEC) {
-          if (wc) st16(t.cons, vi, Vec<W>::pack(cv), nt);
+          const uint32_t so = (uint32_t)u * nth + tid;  // vector index within the step
+          if (wc) {
+            if (nt) __builtin_amdgcn_raw_buffer_store_b128(Vec<W>::pack(cv), rc, so * 16u, 0, kStreamStorePolicy);
+            else reinterpret_cast<u32x4 *>(t.cons)[vi] = Vec<W>::pack(cv);
+          }
           if (wm) {
-            if constexpr (V == 4) st_nt(reinterpret_cast<uint32_t *>(t.mask) + vi, mbs, nt);
-            else st_nt(reinterpret_cast<uint16_t *>(t.mask) + vi, (uint16_t)mbs, nt);
+            if constexpr (V == 4) {
+              if (nt) __builtin_amdgcn_raw_buffer_store_b32(mbs, rm, so * 4u, 0, kStreamStorePolicy);
+              else reinterpret_cast<uint32_t *>(t.mask)[vi] = mbs;
+            } else {
+              if (nt) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)mbs, rm, so * 2u, 0, kStreamStorePolicy);
+              else reinterpret_cast<uint16_t *>(t.mask)[vi] = (uint16_t)mbs;
+            }
           }
         } else {
           if (wc) st_nt(reinterpret_cast<W *>(t.cons) + vi, cv[0], nt);
