@@ -151,22 +151,30 @@ def bench_small(ftv, ctx, sets=32, calls=256):
     for i in range(sets):
         ftv.vote(ctx, reps[i], tol, *outs[i])
     torch.cuda.synchronize()
-    # one call at a time: the events bracket the vote's two kernels and their
-    # launch on an idle device, i.e. the latency of one small vote
+    # one call at a time: the events bracket one ftv_vote call through the C
+    # ABI (descriptors built beforehand), i.e. its two kernels and their launch
+    # on an idle device
+    import ctypes
+    L = ftv.load()
+    stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(int(stream.cuda_stream))
+    descs = [ftv.make_desc(reps[i], tol, *outs[i]) for i in range(sets)]
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
     for c in range(calls):
-        i = c % sets
-        ev[c][0].record()
-        ftv.vote(ctx, reps[i], tol, *outs[i])
-        ev[c][1].record()
+        d = descs[c % sets]
+        ev[c][0].record(stream)
+        rc = L.ftv_vote(ctx.handle, ctypes.byref(d), sh)
+        ev[c][1].record(stream)
         ev[c][1].synchronize()
+        if rc != 0:
+            raise RuntimeError(f"ftv_vote failed: {L.ftv_last_error().decode()}")
     lat = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
     us = lat[len(lat) // 2]
     same = all(torch.equal(outs[i][0].view(torch.int32), outs[0][0].view(torch.int32)) for i in range(sets))
     del reps, outs
     torch.cuda.empty_cache()
     return {"workload": f"k=3 fp32 n=2^20 (the parity workload), {sets} input copies cycled "
-                        f"({sets * 16} MiB, beyond the 256 MB MALL)",
+                        f"({sets * 16} MiB, beyond the 256 MB MALL); one ftv_vote call through the C ABI",
             "us_per_vote_median": round(us, 2), "us_p99": round(lat[int(0.99 * (len(lat) - 1))], 2),
             "replica_gbps": round(3 * n * 4 / us / 1e3, 1),
             "identical_across_copies": same}

@@ -228,13 +228,16 @@ __device__ __forceinline__ Walk make_walk(uint64_t blk, uint64_t block_bytes) {
   return w;
 }
 
+// Block blockIdx.x of buffer blockIdx.y (one of b.k buffers).
 __global__ __launch_bounds__(kFingerprintT) void k_fingerprint(BlockVoteD b) {
   __shared__ u32x4 lbuf[2][4 * kFingerprintT];
   __shared__ uint64_t sw[kFingerprintT / 64];
   __shared__ uint64_t sroot[1][4];
+  BlockVoteD one = b;
+  one.rep[0] = rep_ptr<FTV_MAX_K>(b, (int)blockIdx.y);
   const Walk w = make_walk(blockIdx.x, b.block_bytes);
-  walk_block<1, false, kFingerprintT>(b, w, lbuf, sw, sroot);
-  if (threadIdx.x == 0) b.fps[blockIdx.x] = lds_tree(sroot[0], w.nsub);
+  walk_block<1, false, kFingerprintT>(one, w, lbuf, sw, sroot);
+  if (threadIdx.x == 0) b.fps[(uint64_t)blockIdx.y * b.nblocks + blockIdx.x] = lds_tree(sroot[0], w.nsub);
 }
 
 // ---- block vote ------------------------------------------------------------
@@ -560,28 +563,38 @@ hipError_t launch_blocks_k(const BlockVoteD &b, int num_cus, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_bytes,
-                              uint64_t *fp_out, hipStream_t s) {
+hipError_t launch_fingerprints(const void *const *bufs, uint32_t m, uint64_t nbytes, uint64_t block_bytes,
+                               uint64_t *fp_out, hipStream_t s) {
   const uint64_t nblocks = (nbytes + block_bytes - 1) / block_bytes;
-  if (nblocks == 0) return hipSuccess;
+  if (nblocks == 0 || m == 0) return hipSuccess;
+  if (m > FTV_MAX_K) return hipErrorInvalidValue;
   const uint64_t nwhole = nbytes / block_bytes;
   if (nwhole) {
     BlockVoteD b;
     memset(&b, 0, sizeof(b));
-    b.rep[0] = buf;
-    b.k = 1;
+    for (uint32_t j = 0; j < m; ++j) b.rep[j] = bufs[j];
+    b.k = m;
     b.nbytes = nbytes;
     b.block_bytes = block_bytes;
     b.nblocks = nblocks;
     b.fps = fp_out;
-    hipLaunchKernelGGL(k_fingerprint, dim3((uint32_t)nwhole), dim3(block_threads(block_bytes, kFingerprintT)), 0, s, b);
+    hipLaunchKernelGGL(k_fingerprint, dim3((uint32_t)nwhole, m), dim3(block_threads(block_bytes, kFingerprintT)), 0,
+                       s, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (nwhole < nblocks)  // the partial last block
-    hipLaunchKernelGGL(k_fingerprint_partial, dim3(1), dim3((uint32_t)(block_bytes / 64)), 0, s, buf, nbytes,
-                       block_bytes, fp_out, nwhole);
-  return hipGetLastError();
+  for (uint32_t j = 0; j < m && nwhole < nblocks; ++j) {  // the partial last blocks
+    hipLaunchKernelGGL(k_fingerprint_partial, dim3(1), dim3((uint32_t)(block_bytes / 64)), 0, s, bufs[j], nbytes,
+                       block_bytes, fp_out + (uint64_t)j * nblocks, nwhole);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_bytes,
+                              uint64_t *fp_out, hipStream_t s) {
+  return launch_fingerprints(&buf, 1, nbytes, block_bytes, fp_out, s);
 }
 
 hipError_t launch_vote_blocks(const BlockVoteD &b, int num_cus, hipStream_t s) {

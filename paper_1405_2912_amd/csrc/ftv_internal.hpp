@@ -97,6 +97,10 @@ hipError_t launch_slots_finalize(const TaskD *tasks, const uint64_t *acc, const 
 // ---- fingerprints and block vote (ftv_blocks.hip) ----------------------
 hipError_t launch_fingerprint(const void *buf, uint64_t nbytes, uint64_t block_bytes,
                               uint64_t *fp_out, hipStream_t s);
+// The fingerprints of m <= FTV_MAX_K buffers of nbytes each in one launch;
+// buffer j's go to fp_out[j * nblocks ...].
+hipError_t launch_fingerprints(const void *const *bufs, uint32_t m, uint64_t nbytes, uint64_t block_bytes,
+                               uint64_t *fp_out, hipStream_t s);
 
 struct BlockVoteD {
   const void *rep[FTV_MAX_K];

@@ -14,6 +14,7 @@
 // ftv_copy.hip (the runtime's copy reached about half its rate on MI355X).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -372,15 +373,24 @@ int ftv_mm_check(ftv_mm *mm, uint32_t area, uint64_t block_bytes, void *stream,
     }
     mm->staging_bytes = a->bytes;
   }
-  for (uint64_t j = 0; j < m; ++j) {
-    const Sib &sb = a->sibs[cands[j]];
-    const void *src = sb.ptr;
-    if (sb.memory == FTV_MEM_HOST) {
-      // stream order keeps the staging copy after the previous fingerprints
-      HIPCHK(hipMemcpyAsync(mm->staging, sb.ptr, a->bytes, hipMemcpyHostToDevice, s));
-      src = mm->staging;
-    }
-    HIPCHK(launch_fingerprint(src, a->bytes, block_bytes, mm->d_fps + j * nblocks, s));
+  // fingerprint rows: device siblings first, up to FTV_MAX_K of them per
+  // launch, then host siblings one at a time through the staging buffer
+  // (stream order keeps each staging copy after the previous fingerprints)
+  std::vector<uint32_t> order;
+  for (uint32_t i : cands)
+    if (a->sibs[i].memory == FTV_MEM_DEVICE) order.push_back(i);
+  const uint64_t ndev = order.size();
+  for (uint32_t i : cands)
+    if (a->sibs[i].memory == FTV_MEM_HOST) order.push_back(i);
+  for (uint64_t j0 = 0; j0 < ndev; j0 += FTV_MAX_K) {
+    const void *bufs[FTV_MAX_K];
+    const uint32_t g = (uint32_t)std::min<uint64_t>(FTV_MAX_K, ndev - j0);
+    for (uint32_t q = 0; q < g; ++q) bufs[q] = a->sibs[order[j0 + q]].ptr;
+    HIPCHK(launch_fingerprints(bufs, g, a->bytes, block_bytes, mm->d_fps + j0 * nblocks, s));
+  }
+  for (uint64_t j = ndev; j < m; ++j) {
+    HIPCHK(hipMemcpyAsync(mm->staging, a->sibs[order[j]].ptr, a->bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_fingerprint(mm->staging, a->bytes, block_bytes, mm->d_fps + j * nblocks, s));
   }
   HIPCHK(launch_fp_vote(mm->d_fps, (uint32_t)m, nblocks, mm->d_res, mm->num_cus, s));
   const size_t res_words = (m + 1) / 2 * 2 + 2;
@@ -391,7 +401,7 @@ int ftv_mm_check(ftv_mm *mm, uint32_t area, uint64_t block_bytes, void *stream,
   out->unresolved = unresolved;
   for (uint64_t j = 0; j < m; ++j)
     if (mm->h_res[j]) {
-      a->sibs[cands[j]].valid = false;
+      a->sibs[order[j]].valid = false;
       out->invalidated++;
     }
   return FTV_OK;
