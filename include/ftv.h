@@ -480,9 +480,12 @@ typedef struct ftv_redundancy_report {
 
 /* `impls` (nimpl >= 2) and `units` are HOST arrays; `units` is updated in
  * place.  `out` (device, n elements of cfg->dtype) receives the consensus of
- * the last vote.  Returns FTV_OK also when no vote resolved (see
- * rep->verdict); FTV_E_INVALID / FTV_E_K / FTV_E_DTYPE on bad arguments,
- * FTV_E_NOMEM, FTV_E_HIP.  Not thread-safe per context. */
+ * the last vote and is complete when the call returns.  The votes use the
+ * context's workspace on a stream of the library's own, so work the caller
+ * enqueued with this context must have completed before the call.  Returns
+ * FTV_OK also when no vote resolved (see rep->verdict); FTV_E_INVALID /
+ * FTV_E_K / FTV_E_DTYPE on bad arguments, FTV_E_NOMEM, FTV_E_HIP.  Not
+ * thread-safe per context. */
 int ftv_run_redundant(ftv_ctx *ctx, const ftv_impl *impls, uint32_t nimpl, ftv_unit *units, uint32_t nunits,
                       const ftv_redundancy_cfg *cfg, uint64_t n, void *out, ftv_redundancy_report *rep);
 
