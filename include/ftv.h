@@ -145,11 +145,14 @@ int ftv_vote(ftv_ctx *ctx, const ftv_vote_desc *desc, void *stream);
 
 /* ftv_vote_batch -- ntasks independent votes (any mix of value types, k and
  * tolerances) in ONE persistent kernel launch, replayed from a captured HIP
- * graph.  `descs` is a HOST array.  Each task's results are identical to those
- * of ftv_vote on the same task.  Additional requirement: every replica and
- * consensus pointer 16-byte aligned and every mask pointer 4-byte aligned
- * (FTV_E_ALIGN otherwise).  The host arrays may be reused as soon as the call
- * returns. */
+ * graph (the small-task motivation: Sec. V-A, the voter's best device depends
+ * on the data size).  `descs` is a HOST array.  Each task's results are
+ * identical to those of ftv_vote on the same task.  Additional requirement:
+ * every replica and consensus pointer 16-byte aligned and every mask pointer
+ * 4-byte aligned (FTV_E_ALIGN otherwise).  The host arrays may be reused as
+ * soon as the call returns.  Errors: those of ftv_vote for the first invalid
+ * descriptor (its index in ftv_last_error), FTV_E_INVALID (NULL array, more
+ * than 2^32 - 1 tasks or tiles), FTV_E_NOMEM (table growth), FTV_E_HIP. */
 int ftv_vote_batch(ftv_ctx *ctx, const ftv_vote_desc *descs, uint64_t ntasks, void *stream);
 
 /* Schedule of the batched launch, chosen by ftv_tune_batch.  None of these
@@ -164,7 +167,9 @@ typedef struct ftv_batch_cfg {
                           type, tolerance and k, largest first within a
                           group (co-resident workgroups then run the same
                           code) */
-  uint32_t nt_stores;  /* 1 = non-temporal stores for consensus and mask */
+  uint32_t nt_stores;  /* 1 = streaming stores for consensus and mask
+                          (non-temporal, agent scope: written through the
+                          L2), 0 = ordinary stores */
   uint32_t reserved;
 } ftv_batch_cfg;
 
@@ -220,8 +225,12 @@ typedef struct ftv_block_stats {
  * nbytes: a multiple of the element size.  block_bytes: power of two in
  * [4096, 65536].  fps: k * nblocks uint64 (replica-major) or NULL.
  * blockmap: nblocks bytes: bit r = replica r's fingerprint differs from the
- * source's, bit 7 = no fingerprint majority.  consensus: nbytes.  mask: n bytes
- * or NULL; 0 outside fallback blocks, element-vote mask inside them. */
+ * source's, bit 7 = no fingerprint majority.  consensus: nbytes, 16-byte
+ * aligned.  mask: n bytes (4-byte aligned) or NULL; 0 outside fallback blocks,
+ * element-vote mask inside them.  bstats: device, 8-byte aligned.
+ * Errors: FTV_E_INVALID (NULL argument, block size, nbytes not a multiple of
+ * the element size, more than 2^31 - 1 blocks), FTV_E_K, FTV_E_DTYPE (also an
+ * illegal fallback tolerance), FTV_E_ALIGN, FTV_E_HIP. */
 int ftv_vote_blocks(ftv_ctx *ctx, const void *const *replicas, uint32_t k, int32_t dtype,
                     uint64_t nbytes, uint64_t block_bytes, const ftv_tol *fallback_tol,
                     uint64_t *fps, uint8_t *blockmap, void *consensus, uint8_t *mask,
@@ -292,6 +301,9 @@ typedef struct ftv_server_stats {
   double replica_gbps;       /* replica bytes voted / busy wall time */
 } ftv_server_stats;
 
+/* Start a server on cfg->device (its own stream and thread); *out receives the
+ * handle.  Errors: FTV_E_INVALID (NULL argument, a field out of range,
+ * reserved != 0), FTV_E_NOMEM (arena or tables), FTV_E_HIP. */
 int ftv_server_create(const ftv_server_cfg *cfg, ftv_server **out);
 /* Enqueue a request; *ticket identifies it.  FTV_E_NOMEM if its footprint
  * alone exceeds the budget, FTV_E_BUSY if the queue is full. */
@@ -300,8 +312,10 @@ int ftv_submit(ftv_server *srv, const ftv_request *req, uint64_t *ticket);
  * FTV_OK with *out filled, FTV_E_NOTREADY, or FTV_E_CLOSED (unknown ticket). */
 int ftv_poll(ftv_server *srv, uint64_t ticket, ftv_result *out, int64_t wait_us);
 /* Forget a completed ticket and return its server-allocated outputs to the
- * budget. */
+ * budget.  FTV_E_NOTREADY if it is still in flight, FTV_E_CLOSED if unknown. */
 int ftv_release(ftv_server *srv, uint64_t ticket);
+/* Counters and latency percentiles so far (host struct).  FTV_E_INVALID on
+ * NULL. */
 int ftv_server_get_stats(ftv_server *srv, ftv_server_stats *out);
 /* Drains in-flight work, then stops the server thread and frees everything. */
 int ftv_server_destroy(ftv_server *srv);
