@@ -601,6 +601,77 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
   }
 }
 
+// One full step of the vector path: vectors [base, base + U*nthreads) all
+// exist, so no lane is masked.  The outputs go out as streaming buffer stores
+// against resources based at the step; a NULL output gets a resource of size
+// zero, whose stores the hardware discards, so the step has no branch on the
+// optional outputs and the loads, votes and stores form one straight block.
+template <int DT, int TOL, int K, int U>
+__device__ __forceinline__ void vote_step_full(const TaskD &t, uint64_t base, Acc<K> &acc) {
+  using W = typename VT<DT>::W;
+  constexpr int V = Vec<W>::V;
+  const uint32_t nth = blockDim.x;
+  const uint32_t tid = threadIdx.x;
+  W x[U][K][V];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t vi = base + (uint64_t)u * nth + tid;
+#pragma unroll
+    for (int r = 0; r < K; ++r) Vec<W>::unpack(ld16(t.rep[r], vi), x[u][r]);
+  }
+  const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void *>(reinterpret_cast<uintptr_t>(t.cons) + base * 16u), (short)0,
+      t.cons ? 0x7fffffff : 0, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void *>(reinterpret_cast<uintptr_t>(t.mask) + base * V), (short)0,
+      t.mask ? 0x7fffffff : 0, 0x00020000);
+  uint32_t need = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    W cv[V];
+    uint32_t mbs = 0;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      W xe[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) xe[r] = x[u][r][e];
+      bool general = false;
+      ElemOut<W> o;
+      if constexpr (K == 2) o = vote_general<DT, TOL, 2>(xe, t.tol);
+      else o = vote_fast<DT, TOL, K>(xe, t.tol, general);
+      need |= (uint32_t)general << (u * V + e);
+      cv[e] = o.cons;
+      mbs |= o.mb << (8 * e);
+      acc.add(!general, o.ne, o.mb);
+    }
+    const uint32_t so = (uint32_t)u * nth + tid;
+    __builtin_amdgcn_raw_buffer_store_b128(Vec<W>::pack(cv), rc, so * 16u, 0, kStreamStorePolicy);
+    if constexpr (V == 4) __builtin_amdgcn_raw_buffer_store_b32(mbs, rm, so * 4u, 0, kStreamStorePolicy);
+    else __builtin_amdgcn_raw_buffer_store_b16((uint16_t)mbs, rm, so * 2u, 0, kStreamStorePolicy);
+  }
+  // fix-up pass (rare), as in vote_range
+  if constexpr (K >= 3) {
+    if (__ballot(need != 0u) != 0ull) {
+      __threadfence_block();
+#pragma unroll 1
+      for (int q = 0; q < U * V; ++q) {
+        const bool mine = (need >> q) & 1u;
+        ElemOut<W> o{};
+        if (mine) {
+          const uint64_t i = (base + (uint64_t)(q / V) * nth + tid) * V + (uint64_t)(q % V);
+          W xe[K];
+#pragma unroll
+          for (int r = 0; r < K; ++r) xe[r] = reinterpret_cast<const W *>(t.rep[r])[i];
+          o = vote_slow<DT, TOL, K>(xe, t.tol, t.rep, i);
+          if (t.cons) reinterpret_cast<W *>(t.cons)[i] = o.cons;
+          if (t.mask) t.mask[i] = (uint8_t)o.mb;
+        }
+        acc.add(mine, o.ne, o.mb);
+      }
+    }
+  }
+}
+
 // Elements [nvec*V, n) of a vector-path task (fewer than V), one per lane.
 template <int DT, int TOL, int K>
 __device__ __forceinline__ void vote_tail(const TaskD &t, Acc<K> &acc) {

@@ -23,26 +23,77 @@ namespace {
 
 using namespace dev;
 
-// Launch shape: one workgroup of 512 threads per CU.  On MI355X, with the
-// replicas' own (random) data, this streamed the k = 3 fp32 vote at 0.795 ms
-// against 0.826 ms for two 256-thread workgroups per CU (the same waves per
-// CU): a step of a workgroup then covers 16 KiB of every replica instead of
-// 8 KiB, and fewer concurrent streams keep more DRAM page locality.  More
-// waves per CU, or more vectors in flight per lane, measured slower.
-constexpr int kVoteThreads = 512;
+// Launch shape: one workgroup per CU, looping over tiles of `threads` x U
+// vectors (grid-stride).  The threads per workgroup and the vectors per lane
+// and step depend on the replica count and the element size; the values are
+// those a sweep on MI355X found fastest for the vote of replicas that differ
+// in few elements (k = 2..7, 4- and 8-byte elements, 1 GiB and 512 MiB per
+// replica): for k = 3 fp32, 256 threads with four vectors in flight per lane
+// and replica streamed at 0.76 ms against 0.79 ms for 512 threads with two.
+// Full tiles go through the branch-free step of vote_step_full; where the
+// sweep found the general step as fast (k = 4, and k = 3 and 6 with 8-byte
+// elements) every tile uses vote_range.  Bit-wise (EXACT) votes keep 512
+// threads and the general step: their cheaper compare measured faster that way
+// (k = 3 int32: 0.74 ms against 0.80 ms).  More workgroups per CU measured
+// slower throughout: longer contiguous steps and fewer concurrent streams keep
+// DRAM page locality, and a grid larger than what is resident leaves a tail.
+struct VoteShape {
+  int threads;
+  int unroll;
+  bool lean;
+};
+constexpr VoteShape vote_shape(int es, int tol, int k) {
+  if (tol == FTV_TOL_EXACT) return {512, k <= 3 ? 2 : 1, false};
+  if (es == 4) {
+    switch (k) {
+      case 2: return {256, 4, true};
+      case 3: return {256, 4, true};
+      case 4: return {512, 1, false};
+      case 5: return {256, 2, true};
+      case 6: return {256, 2, true};
+      default: return {256, 1, true};
+    }
+  }
+  switch (k) {
+    case 2: return {256, 4, true};
+    case 3: return {512, 2, false};
+    case 4: return {512, 1, false};
+    case 5: return {512, 2, true};
+    case 6: return {512, 1, false};
+    default: return {256, 1, true};
+  }
+}
 constexpr int kVoteWgPerCu = 1;
 
 template <int DT, int TOL, int K, bool VEC>
-__global__ __launch_bounds__(kVoteThreads) void k_vote_task(TaskD t, VoteWs ws) {
+struct TaskShape {
+  static constexpr VoteShape s =
+      VEC ? vote_shape(sizeof(typename VT<DT>::W), TOL, K) : VoteShape{512, Unroll<K>::value, false};
+  static constexpr int threads = s.threads;
+  static constexpr int U = s.unroll;
+  static constexpr bool lean = s.lean;
+};
+
+template <int DT, int TOL, int K, bool VEC>
+__global__ __launch_bounds__((TaskShape<DT, TOL, K, VEC>::threads)) void k_vote_task(TaskD t, VoteWs ws) {
   __shared__ uint64_t sh[16 * kNumCounters];
-  constexpr int U = Unroll<K>::value;
+  using S = TaskShape<DT, TOL, K, VEC>;
+  constexpr int U = S::U;
   constexpr int NC = Acc<K>::NC;
   Acc<K> acc;
   acc.zero();
   const uint64_t tile = (uint64_t)blockDim.x * U;
-  for (uint64_t b = (uint64_t)blockIdx.x * tile; b < t.nvec; b += (uint64_t)gridDim.x * tile) {
-    const uint64_t e = b + tile < t.nvec ? b + tile : t.nvec;
-    vote_range<DT, TOL, K, VEC, U>(t, b, e, acc, true);
+  if constexpr (S::lean) {
+    // full tiles grid-stride, then the partial tile (if any) by its owner
+    const uint64_t nfull = t.nvec / tile;
+    for (uint64_t i = blockIdx.x; i < nfull; i += gridDim.x) vote_step_full<DT, TOL, K, U>(t, i * tile, acc);
+    if (nfull * tile < t.nvec && blockIdx.x == nfull % gridDim.x)
+      vote_range<DT, TOL, K, VEC, U>(t, nfull * tile, t.nvec, acc, true);
+  } else {
+    for (uint64_t b = (uint64_t)blockIdx.x * tile; b < t.nvec; b += (uint64_t)gridDim.x * tile) {
+      const uint64_t e = b + tile < t.nvec ? b + tile : t.nvec;
+      vote_range<DT, TOL, K, VEC, U>(t, b, e, acc, true);
+    }
   }
   if constexpr (VEC) {
     if (blockIdx.x == gridDim.x - 1) vote_tail<DT, TOL, K>(t, acc);
@@ -63,13 +114,13 @@ __global__ __launch_bounds__(64) void k_vote_finalize(TaskD t, VoteWs ws) {
 // start, a larger grid leaves a second, mostly empty wave of workgroups.
 template <int DT, int TOL, int K, bool VEC>
 hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
-  constexpr int U = Unroll<K>::value;
-  const uint64_t tile = (uint64_t)kVoteThreads * U;
+  using S = TaskShape<DT, TOL, K, VEC>;
+  const uint64_t tile = (uint64_t)S::threads * S::U;
   const uint64_t tiles = (t.nvec + tile - 1) / tile;
   uint64_t cap = (uint64_t)num_cus * kVoteWgPerCu;
   if (cap > (uint64_t)kMaxGrid) cap = kMaxGrid;
   const uint32_t grid = (uint32_t)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
-  hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(kVoteThreads), 0, s, t, ws);
+  hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(S::threads), 0, s, t, ws);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vote_finalize, dim3(1), dim3(64), 0, s, t, ws);
