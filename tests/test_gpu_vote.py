@@ -147,6 +147,24 @@ def test_optional_outputs(gpu, ctx):
         _check(_run(gpu, ctx, reps, gpu.ulp(4), want_cons=wc, want_mask=wm), ref, 3, "optional")
 
 
+@pytest.mark.parametrize("dtype,k", [(np.float32, 2), (np.float32, 3), (np.float32, 5), (np.float32, 7),
+                                     (np.float64, 2), (np.float64, 5), (np.float64, 7)])
+def test_full_steps_and_optional_outputs(gpu, ctx, dtype, k):
+    """Many full tiles of each launch shape, a partial tile and a ragged tail,
+    under ULP and REL, with every combination of the optional outputs (a
+    missing output's stores go to a zero-size buffer resource)."""
+    rng = np.random.default_rng(500 + k)
+    n = 200003
+    reps = _replicas(rng, dtype, k, n)
+    m = 4 if dtype == np.float32 else 2
+    for tol_o, tol_f in ((oracle.ulp(m), gpu.ulp(m)), (oracle.rel(1e-3), gpu.rel(1e-3))):
+        ref = oracle.vote(reps, tol_o)
+        for wc, wm in ((True, True), (False, True), (True, False), (False, False)):
+            where = f"{np.dtype(dtype).name} k={k} tol={tol_o} consensus={wc} mask={wm}"
+            print("case:", where, flush=True)
+            _check(_run(gpu, ctx, reps, tol_f, want_cons=wc, want_mask=wm), ref, k, where)
+
+
 def test_repeat_is_deterministic(gpu, ctx):
     reps = synth.small_task_set(n=300001)
     a = _run(gpu, ctx, reps, gpu.ulp(4))
