@@ -126,6 +126,13 @@ struct ftv_ctx {
   // ftv_run_redundant: replicas abandoned after a timeout, freed once their
   // work has finished (ftv_run.cpp)
   RunState *run = nullptr;
+  // ftv_vote_mem: two device staging sets for host replicas, their copy
+  // stream and the events that order copies and votes
+  char *stage = nullptr;
+  uint64_t stage_bytes = 0;
+  hipStream_t copy_stream{};
+  hipEvent_t mem_entry{}, mem_copied[2]{}, mem_consumed[2]{};
+  bool mem_ready = false;
 };
 
 namespace {
@@ -420,6 +427,15 @@ int ftv_ctx_destroy(ftv_ctx *c) {
   if (c->blk_acc) (void)hipFree(c->blk_acc);
   if (c->staged) (void)hipEventDestroy(c->staged);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->mem_ready) {
+    (void)hipEventDestroy(c->mem_entry);
+    for (int j = 0; j < 2; ++j) {
+      (void)hipEventDestroy(c->mem_copied[j]);
+      (void)hipEventDestroy(c->mem_consumed[j]);
+    }
+    (void)hipStreamDestroy(c->copy_stream);
+  }
+  if (c->stage) (void)hipFree(c->stage);
   delete c;
   return FTV_OK;
 }
@@ -434,6 +450,119 @@ int ftv_vote(ftv_ctx *c, const ftv_vote_desc *desc, void *stream) {
   if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
   return FTV_OK;
 }
+
+}  // extern "C"
+namespace {
+int mem_pieces(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, const TaskD &t, const VoteWs &ws,
+               bool vec, uint64_t es, uint64_t chunk, uint64_t set_bytes, uint32_t nhost, hipStream_t s);
+}  // namespace
+extern "C" {
+
+int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, uint64_t chunk_bytes,
+                 void *stream) {
+  if (!c) return fail(FTV_E_INVALID, "NULL context");
+  if (!desc || !memory) return fail(FTV_E_INVALID, "NULL argument");
+  TaskD t;
+  int rc = make_task(desc, false, &t);
+  if (rc) return rc;
+  uint32_t nhost = 0;
+  for (uint32_t r = 0; r < desc->k; ++r) {
+    if (memory[r] != FTV_MEM_HOST && memory[r] != FTV_MEM_DEVICE)
+      return fail(FTV_E_INVALID, "memory[r] must be FTV_MEM_HOST or FTV_MEM_DEVICE");
+    nhost += memory[r] == FTV_MEM_HOST;
+  }
+  if (nhost == 0 || desc->n == 0) return ftv_vote(c, desc, stream);
+  if (chunk_bytes < (1u << 20) || chunk_bytes > (1ull << 32))
+    return fail(FTV_E_INVALID, "chunk_bytes must be in [1 MiB, 4 GiB]");
+  // the staged pieces are aligned, so every piece takes the vector path when
+  // the device replicas and the outputs allow it
+  bool vec = (!desc->consensus || (uintptr_t)desc->consensus % 16 == 0) &&
+             (!desc->mask || (uintptr_t)desc->mask % 4 == 0);
+  for (uint32_t r = 0; r < desc->k; ++r)
+    if (memory[r] == FTV_MEM_DEVICE) vec = vec && (uintptr_t)desc->replicas[r] % 16 == 0;
+  const uint64_t es = (uint64_t)elem_size(desc->dtype);
+  const uint64_t chunk = chunk_bytes / es / 4096 * 4096;  // elements per piece (whole vectors)
+  const uint64_t set_bytes = (chunk * es + 255) / 256 * 256 * nhost;
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->mem_ready) {
+    bool ok = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->mem_entry, hipEventDisableTiming) == hipSuccess;
+    for (int j = 0; j < 2; ++j)
+      ok = ok && hipEventCreateWithFlags(&c->mem_copied[j], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&c->mem_consumed[j], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      return fail(FTV_E_HIP, "cannot create the staging stream and events");
+    }
+    c->mem_ready = true;
+  }
+  if (c->stage_bytes < 2 * set_bytes) {
+    HIPCHK(hipStreamSynchronize(s));  // the old staging may still be read
+    HIPCHK(hipStreamSynchronize(c->copy_stream));
+    if (c->stage) (void)hipFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    if (hipMalloc(&c->stage, 2 * set_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      c->stage = nullptr;
+      return fail(FTV_E_NOMEM, "cannot allocate the staging buffers");
+    }
+    c->stage_bytes = 2 * set_bytes;
+  }
+  VoteWs ws{c->partials};
+  // copies into a staging set wait for the votes that last read it: the
+  // previous calls' (this entry event) and the piece two before
+  HIPCHK(hipEventRecord(c->mem_entry, s));
+  HIPCHK(hipStreamWaitEvent(c->copy_stream, c->mem_entry, 0));
+  rc = mem_pieces(c, desc, memory, t, ws, vec, es, chunk, set_bytes, nhost, s);
+  if (rc != FTV_OK) {
+    // leave the accumulators zeroed for the next call
+    (void)hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * kNumCounters, s);
+    return rc;
+  }
+  hipError_t e = launch_vote_finalize(t, ws, s);
+  if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
+  return FTV_OK;
+}
+
+}  // extern "C"
+namespace {
+// The pieces of an ftv_vote_mem call: copy, vote without finalizing.
+int mem_pieces(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, const TaskD &t, const VoteWs &ws,
+               bool vec, uint64_t es, uint64_t chunk, uint64_t set_bytes, uint32_t nhost, hipStream_t s) {
+  const uint64_t n = desc->n;
+  for (uint64_t off = 0, i = 0; off < n; off += chunk, ++i) {
+    const int j = (int)(i & 1);
+    const uint64_t len = std::min<uint64_t>(chunk, n - off);
+    if (i >= 2) HIPCHK(hipStreamWaitEvent(c->copy_stream, c->mem_consumed[j], 0));
+    char *set = c->stage + (uint64_t)j * set_bytes;
+    TaskD tc = t;
+    uint32_t h = 0;
+    for (uint32_t r = 0; r < desc->k; ++r) {
+      const char *src = reinterpret_cast<const char *>(desc->replicas[r]) + off * es;
+      if (memory[r] == FTV_MEM_HOST) {
+        char *dst = set + (uint64_t)h++ * (set_bytes / nhost);
+        HIPCHK(hipMemcpyAsync(dst, src, len * es, hipMemcpyHostToDevice, c->copy_stream));
+        tc.rep[r] = dst;
+      } else {
+        tc.rep[r] = src;
+      }
+    }
+    HIPCHK(hipEventRecord(c->mem_copied[j], c->copy_stream));
+    HIPCHK(hipStreamWaitEvent(s, c->mem_copied[j], 0));
+    tc.cons = desc->consensus ? reinterpret_cast<char *>(desc->consensus) + off * es : nullptr;
+    tc.mask = desc->mask ? desc->mask + off : nullptr;
+    tc.n = len;
+    tc.vec = vec ? 1u : 0u;
+    tc.nvec = vec ? len / (16 / es) : len;
+    hipError_t e = launch_vote_task(tc, ws, c->num_cus, s, false);
+    if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
+    HIPCHK(hipEventRecord(c->mem_consumed[j], s));
+  }
+  return FTV_OK;
+}
+}  // namespace
+extern "C" {
 
 int ftv_vote_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void *stream) {
   if (!c) return fail(FTV_E_INVALID, "NULL context");

@@ -58,13 +58,19 @@ int elem_size(int dtype);
 
 // ---- launchers (ftv_vote_*.hip) -----------------------------------------
 // The vote kernel followed by a one-workgroup finalize kernel on the same
-// stream (stats record from the accumulators, accumulators cleared).
-hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
+// stream (stats record from the accumulators, accumulators cleared).  With
+// finalize = false only the vote kernel: its counts stay in the accumulators,
+// to be added to by further launches (pieces of one task) and finalized by
+// launch_vote_finalize.
+hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize = true);
 // The same per value type (one translation unit each).
-hipError_t launch_vote_task_f32(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
-hipError_t launch_vote_task_f64(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
-hipError_t launch_vote_task_i32(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
-hipError_t launch_vote_task_i64(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s);
+hipError_t launch_vote_task_f32(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize);
+hipError_t launch_vote_task_f64(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize);
+hipError_t launch_vote_task_i32(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize);
+hipError_t launch_vote_task_i64(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize);
+// Stats record of task t (t.n, t.k, t.stats) from the accumulators, which it
+// clears (ftv_vote_batch.hip).
+hipError_t launch_vote_finalize(const TaskD &t, const VoteWs &ws, hipStream_t s);
 
 // A persistent launch over a queue of tiles.  Two ways to name the tiles:
 //  * prefix mode (batched calls): prefix[t] = first tile of task t (ntasks+1

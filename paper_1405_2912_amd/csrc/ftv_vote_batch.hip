@@ -145,16 +145,27 @@ __global__ __launch_bounds__(64) void k_slots_finalize(const TaskD *tasks, const
   }
 }
 
+// Stats record of one task assembled from several vote launches.
+__global__ __launch_bounds__(64) void k_task_finalize(TaskD t, VoteWs ws) {
+  __shared__ uint64_t s_tot[kNumCounters];
+  finalize_task(t, ws.acc, true, s_tot);
+}
+
 }  // namespace
 
-hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+hipError_t launch_vote_task(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize) {
   switch ((int)(t.spec / 24)) {
-    case FTV_F32: return launch_vote_task_f32(t, ws, num_cus, s);
-    case FTV_F64: return launch_vote_task_f64(t, ws, num_cus, s);
-    case FTV_I32: return launch_vote_task_i32(t, ws, num_cus, s);
-    case FTV_I64: return launch_vote_task_i64(t, ws, num_cus, s);
+    case FTV_F32: return launch_vote_task_f32(t, ws, num_cus, s, finalize);
+    case FTV_F64: return launch_vote_task_f64(t, ws, num_cus, s, finalize);
+    case FTV_I32: return launch_vote_task_i32(t, ws, num_cus, s, finalize);
+    case FTV_I64: return launch_vote_task_i64(t, ws, num_cus, s, finalize);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_vote_finalize(const TaskD &t, const VoteWs &ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_task_finalize, dim3(1), dim3(64), 0, s, t, ws);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s) {

@@ -3,8 +3,8 @@
 
 namespace ftv {
 
-hipError_t launch_vote_task_i64(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
-  return launch_vec<FTV_I64, FTV_TOL_EXACT>(t, ws, num_cus, s);
+hipError_t launch_vote_task_i64(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize) {
+  return launch_vec<FTV_I64, FTV_TOL_EXACT>(t, ws, num_cus, s, finalize);
 }
 
 }  // namespace ftv

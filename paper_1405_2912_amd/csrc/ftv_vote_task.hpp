@@ -113,7 +113,7 @@ __global__ __launch_bounds__(64) void k_vote_finalize(TaskD t, VoteWs ws) {
 // the grid-stride loop is only balanced when every workgroup runs from the
 // start, a larger grid leaves a second, mostly empty wave of workgroups.
 template <int DT, int TOL, int K, bool VEC>
-hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize) {
   using S = TaskShape<DT, TOL, K, VEC>;
   const uint64_t tile = (uint64_t)S::threads * S::U;
   const uint64_t tiles = (t.nvec + tile - 1) / tile;
@@ -122,28 +122,28 @@ hipError_t launch_one(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t
   const uint32_t grid = (uint32_t)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
   hipLaunchKernelGGL((k_vote_task<DT, TOL, K, VEC>), dim3(grid), dim3(S::threads), 0, s, t, ws);
   const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !finalize) return e;
   hipLaunchKernelGGL(k_vote_finalize, dim3(1), dim3(64), 0, s, t, ws);
   return hipGetLastError();
 }
 
 template <int DT, int TOL, bool VEC>
-hipError_t launch_k(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
+hipError_t launch_k(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize) {
   switch (t.k) {
-    case 2: return launch_one<DT, TOL, 2, VEC>(t, ws, num_cus, s);
-    case 3: return launch_one<DT, TOL, 3, VEC>(t, ws, num_cus, s);
-    case 4: return launch_one<DT, TOL, 4, VEC>(t, ws, num_cus, s);
-    case 5: return launch_one<DT, TOL, 5, VEC>(t, ws, num_cus, s);
-    case 6: return launch_one<DT, TOL, 6, VEC>(t, ws, num_cus, s);
-    case 7: return launch_one<DT, TOL, 7, VEC>(t, ws, num_cus, s);
+    case 2: return launch_one<DT, TOL, 2, VEC>(t, ws, num_cus, s, finalize);
+    case 3: return launch_one<DT, TOL, 3, VEC>(t, ws, num_cus, s, finalize);
+    case 4: return launch_one<DT, TOL, 4, VEC>(t, ws, num_cus, s, finalize);
+    case 5: return launch_one<DT, TOL, 5, VEC>(t, ws, num_cus, s, finalize);
+    case 6: return launch_one<DT, TOL, 6, VEC>(t, ws, num_cus, s, finalize);
+    case 7: return launch_one<DT, TOL, 7, VEC>(t, ws, num_cus, s, finalize);
   }
   return hipErrorInvalidValue;
 }
 
 template <int DT, int TOL>
-hipError_t launch_vec(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s) {
-  return t.vec ? launch_k<DT, TOL, true>(t, ws, num_cus, s)
-               : launch_k<DT, TOL, false>(t, ws, num_cus, s);
+hipError_t launch_vec(const TaskD &t, const VoteWs &ws, int num_cus, hipStream_t s, bool finalize) {
+  return t.vec ? launch_k<DT, TOL, true>(t, ws, num_cus, s, finalize)
+               : launch_k<DT, TOL, false>(t, ws, num_cus, s, finalize);
 }
 
 }  // namespace

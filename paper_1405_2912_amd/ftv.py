@@ -128,7 +128,7 @@ EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv
            "ftv_submit", "ftv_poll", "ftv_release", "ftv_server_get_stats",
            "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote",
            "ftv_mm_create", "ftv_mm_destroy", "ftv_mm_register", "ftv_mm_request", "ftv_mm_release",
-           "ftv_mm_siblings", "ftv_mm_check", "ftv_run_redundant"]
+           "ftv_mm_siblings", "ftv_mm_check", "ftv_run_redundant", "ftv_vote_mem"]
 
 _lib = None
 
@@ -157,6 +157,7 @@ def load():
     L.ftv_ctx_destroy.argtypes = [vp]
     L.ftv_vote.argtypes = [vp, POINTER(VoteDesc), vp]
     L.ftv_vote_batch.argtypes = [vp, POINTER(VoteDesc), c_uint64, vp]
+    L.ftv_vote_mem.argtypes = [vp, POINTER(VoteDesc), POINTER(ctypes.c_int32), c_uint64, vp]
     L.ftv_batch_get_config.argtypes = [vp, POINTER(BatchCfg)]
     L.ftv_batch_set_config.argtypes = [vp, POINTER(BatchCfg)]
     L.ftv_tune_batch.argtypes = [vp, POINTER(VoteDesc), c_uint64, vp, c_uint32, POINTER(BatchCfg)]
@@ -309,6 +310,26 @@ def vote(ctx: Context, replicas, tol: Tol, consensus=None, mask=None, stats=None
         stats = stats_tensor(x0.device)
     d = make_desc(replicas, tol, consensus, mask, stats)
     _check(load().ftv_vote(ctx.handle, ctypes.byref(d), c_void_p(_stream_handle(stream))))
+    return consensus, mask, stats
+
+
+def vote_mem(ctx: Context, replicas, tol: Tol, consensus=None, mask=None, stats=None, chunk_bytes: int = 64 << 20,
+             stream=None, want_consensus: bool = True, want_mask: bool = True):
+    """ftv_vote_mem: replicas are torch tensors in host memory (CPU tensors,
+    pinned or not) or on the GPU; outputs are device tensors."""
+    torch = _torch()
+    dev = next((r.device for r in replicas if r.is_cuda), torch.device("cuda", torch.cuda.current_device()))
+    x0 = replicas[0]
+    if consensus is None and want_consensus:
+        consensus = torch.empty(x0.numel(), dtype=x0.dtype, device=dev)
+    if mask is None and want_mask:
+        mask = torch.empty(x0.numel(), dtype=torch.uint8, device=dev)
+    if stats is None:
+        stats = stats_tensor(dev)
+    d = make_desc(replicas, tol, consensus, mask, stats)
+    mem = (ctypes.c_int32 * len(replicas))(*[MEM_DEVICE if r.is_cuda else MEM_HOST for r in replicas])
+    _check(load().ftv_vote_mem(ctx.handle, ctypes.byref(d), mem, c_uint64(int(chunk_bytes)),
+                               c_void_p(_stream_handle(stream))))
     return consensus, mask, stats
 
 
