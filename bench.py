@@ -436,6 +436,58 @@ def bench_siblings(ftv, gib: int = 2):
 # ---------------------------------------------------------------------------
 # redundant execution (DMR) of the single large task, with deadlines
 # ---------------------------------------------------------------------------
+def bench_mixed(ftv, ctx, side=16384, reps_timed=3, chunk_mib=64):
+    """k=3 fp32 16384x16384 with replica 1 in host memory (a CPU run's result)
+    and replicas 0 and 2 in HBM: ftv_vote_mem, beside a plain copy of the host
+    replica to the device (the link's rate) and ftv_vote with all three in HBM."""
+    import torch
+    import synth.device as sd
+    n = side * side
+    log("bench: mixed-memory vote (one replica in host memory)")
+    reps = sd.large_task_set(n, "f32")
+    cons = torch.empty_like(reps[0])
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = ftv.stats_tensor("cuda")
+    tol = ftv.ulp(4)
+    out = {"workload": f"k=3 fp32 {side}x{side} (1 GiB per replica), replica 1 in host memory, "
+                       f"{chunk_mib} MiB pieces"}
+    ref = None
+    for kind in ("pinned", "pageable"):
+        host = torch.empty(n, dtype=torch.float32, pin_memory=(kind == "pinned"))
+        host.copy_(reps[1])
+        torch.cuda.synchronize()
+        mixed = [reps[0], host, reps[2]]
+        ftv.vote_mem(ctx, mixed, tol, cons, mask, st, chunk_bytes=chunk_mib << 20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps_timed):
+            ftv.vote_mem(ctx, mixed, tol, cons, mask, st, chunk_bytes=chunk_mib << 20)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps_timed * 1e3
+        dev = torch.empty_like(reps[1])
+        dev.copy_(host, non_blocking=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps_timed):
+            dev.copy_(host, non_blocking=True)
+        torch.cuda.synchronize()
+        copy_ms = (time.perf_counter() - t0) / reps_timed * 1e3
+        if ref is None:
+            ftv.vote(ctx, reps, tol, cons, mask, st)
+            torch.cuda.synchronize()
+            ref = st.clone()
+            ftv.vote_mem(ctx, mixed, tol, cons, mask, st, chunk_bytes=chunk_mib << 20)
+            torch.cuda.synchronize()
+        out[kind] = {"ms": round(ms, 3), "host_replica_gbps": round(n * 4 / ms / 1e6, 1),
+                     "h2d_copy_ms": round(copy_ms, 3), "h2d_copy_gbps": round(n * 4 / copy_ms / 1e6, 1),
+                     "vote_over_copy": round(ms / copy_ms, 3)}
+        del host, dev
+    out["stats_equal_all_device_vote"] = bool(torch.equal(ref, st))
+    del reps, cons, mask
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_redundant(ftv, ctx, side=16384, calls=7):
     """Three implementations of the 1 GiB fp32 task (stand-ins: each copies one
     of the large task's replicas into its output), DMR on the two with the
@@ -551,7 +603,7 @@ def main():
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
-    ap.add_argument("--only", choices=["batched", "blocks"],
+    ap.add_argument("--only", choices=["batched", "blocks", "mixed"],
                     help="run only this workload and print its result (for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -572,7 +624,8 @@ def main():
         del src, dst
     if args.only:
         run = {"batched": lambda: bench_batched(ftv, ctx, args.batch_tasks),
-               "blocks": lambda: bench_blocks(ftv, ctx)}[args.only]
+               "blocks": lambda: bench_blocks(ftv, ctx),
+               "mixed": lambda: bench_mixed(ftv, ctx)}[args.only]
         res = run()
         ctx.close()
         print(json.dumps({args.only: res}), flush=True)
@@ -617,6 +670,7 @@ def main():
         out["blocks"] = bench_blocks(ftv, ctx)
         out["siblings"] = bench_siblings(ftv)
         out["redundant"] = bench_redundant(ftv, ctx)
+        out["mixed_memory"] = bench_mixed(ftv, ctx)
         out["serving"] = bench_serving(ftv, ctx, args.serve_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
