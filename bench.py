@@ -607,8 +607,8 @@ def main():
                     help="run only this workload and print its result (for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the voter's multi-GPU "
-              "sharding is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding the "
+              "voter across GPUs is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
