@@ -532,7 +532,7 @@ def bench_redundant(ftv, ctx, side=16384, calls=7):
 # ---------------------------------------------------------------------------
 # serving: Poisson arrivals, continuous batching, p50/p99 latency
 # ---------------------------------------------------------------------------
-def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int = 128):
+def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int = 128, count: int = None):
     """chunk_mib: bytes per replica a request advances per iteration.  On
     MI355X, 32 / 64 / 128 / 256 MiB gave p99 593 / 496 / 373 / 338 us at the
     same p50 (97 us); 128 MiB keeps more iterations shared between requests."""
@@ -545,7 +545,7 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
     srv = ftv.Server(hbm_budget_bytes=64 << 30, arena_bytes=24 << 30, chunk_bytes=chunk_mib << 20,
                      max_slots=1024, max_queue=1 << 20)
     rng = np.random.default_rng(14052912 + 4)
-    count = int(seconds * rate)
+    count = int(seconds * rate) if count is None else int(count)
     gaps = rng.exponential(1.0 / rate, count)
     sizes = np.floor(np.exp(rng.uniform(np.log(4096), np.log(256 << 20), count)) / 4).astype(np.int64)
     offs = [int(rng.integers(0, (pool_elems - int(n)) // 64 + 1)) * 64 for n in sizes]
@@ -579,8 +579,9 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
     srv.close()
     del pool
     torch.cuda.empty_cache()
-    return {"workload": f"Poisson {rate:.0f} req/s for {seconds:g} s, sizes log-uniform [4 KiB, 256 MiB] per "
+    return {"workload": f"Poisson {rate:.0f} req/s, {count} requests, sizes log-uniform [4 KiB, 256 MiB] per "
                         f"replica, k=3 fp32, budget 64 GiB, {chunk_mib} MiB per replica per iteration",
+            "offered_rate": rate,
             "requests": int(st["completed"]), "p50_us": round(st["p50_us"], 1),
             "p99_us": round(st["p99_us"], 1), "mean_us": round(st["mean_us"], 1),
             "max_us": round(st["max_us"], 1), "mean_queue_depth": round(st["mean_queue_depth"], 3),
@@ -589,6 +590,20 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
             "max_requests_per_iteration": int(st["max_requests_per_iteration"]),
             "served_replica_gbps": round(st["replica_gbps"], 2),
             "peak_bytes_in_flight": int(st["peak_bytes_in_flight"])}
+
+
+def bench_serving_ramp(ftv, ctx, seconds: float = 2.0):
+    """The serving workload at rising offered rates, and all requests at once
+    (the server's saturated throughput)."""
+    keys = ("requests", "p50_us", "p99_us", "mean_queue_depth", "peak_queue_depth", "served_replica_gbps",
+            "max_requests_per_iteration")
+    out = []
+    for rate in (8000.0, 16000.0):
+        r = bench_serving(ftv, ctx, seconds, rate)
+        out.append(dict({"offered_rate": rate}, **{k: r[k] for k in keys}))
+    r = bench_serving(ftv, ctx, seconds, 1e9, count=10000)
+    out.append(dict({"offered_rate": "all at once"}, **{k: r[k] for k in keys}))
+    return out
 
 
 def main():
@@ -603,7 +618,7 @@ def main():
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
-    ap.add_argument("--only", choices=["batched", "blocks", "mixed"],
+    ap.add_argument("--only", choices=["batched", "blocks", "mixed", "ramp"],
                     help="run only this workload and print its result (for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -625,7 +640,8 @@ def main():
     if args.only:
         run = {"batched": lambda: bench_batched(ftv, ctx, args.batch_tasks),
                "blocks": lambda: bench_blocks(ftv, ctx),
-               "mixed": lambda: bench_mixed(ftv, ctx)}[args.only]
+               "mixed": lambda: bench_mixed(ftv, ctx),
+               "ramp": lambda: bench_serving_ramp(ftv, ctx)}[args.only]
         res = run()
         ctx.close()
         print(json.dumps({args.only: res}), flush=True)
@@ -672,6 +688,7 @@ def main():
         out["redundant"] = bench_redundant(ftv, ctx)
         out["mixed_memory"] = bench_mixed(ftv, ctx)
         out["serving"] = bench_serving(ftv, ctx, args.serve_seconds)
+        out["serving_ramp"] = bench_serving_ramp(ftv, ctx, min(2.0, args.serve_seconds))
     ctx.close()
     print(json.dumps(out), flush=True)
 
