@@ -285,6 +285,9 @@ class Context:
 def make_desc(replicas, tol: Tol, consensus=None, mask=None, stats=None, n=None) -> VoteDesc:
     d = VoteDesc()
     k = len(replicas)
+    for t in list(replicas) + [x for x in (consensus, mask) if x is not None]:
+        if not t.is_contiguous():
+            raise ValueError("replicas and outputs must be contiguous tensors")
     for r, t in enumerate(replicas):
         d.replicas[r] = t.data_ptr()
     d.k = k
