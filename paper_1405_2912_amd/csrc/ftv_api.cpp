@@ -358,6 +358,41 @@ void cache_store(const std::string &path, const std::string &key, const ftv_batc
   f << "}\n";
 }
 
+// The pieces of an ftv_vote_mem call: copy, vote without finalizing.
+int mem_pieces(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, const TaskD &t, const VoteWs &ws,
+               bool vec, uint64_t es, uint64_t chunk, uint64_t set_bytes, uint32_t nhost, hipStream_t s) {
+  const uint64_t n = desc->n;
+  for (uint64_t off = 0, i = 0; off < n; off += chunk, ++i) {
+    const int j = (int)(i & 1);
+    const uint64_t len = std::min<uint64_t>(chunk, n - off);
+    if (i >= 2) HIPCHK(hipStreamWaitEvent(c->copy_stream, c->mem_consumed[j], 0));
+    char *set = c->stage + (uint64_t)j * set_bytes;
+    TaskD tc = t;
+    uint32_t h = 0;
+    for (uint32_t r = 0; r < desc->k; ++r) {
+      const char *src = reinterpret_cast<const char *>(desc->replicas[r]) + off * es;
+      if (memory[r] == FTV_MEM_HOST) {
+        char *dst = set + (uint64_t)h++ * (set_bytes / nhost);
+        HIPCHK(hipMemcpyAsync(dst, src, len * es, hipMemcpyHostToDevice, c->copy_stream));
+        tc.rep[r] = dst;
+      } else {
+        tc.rep[r] = src;
+      }
+    }
+    HIPCHK(hipEventRecord(c->mem_copied[j], c->copy_stream));
+    HIPCHK(hipStreamWaitEvent(s, c->mem_copied[j], 0));
+    tc.cons = desc->consensus ? reinterpret_cast<char *>(desc->consensus) + off * es : nullptr;
+    tc.mask = desc->mask ? desc->mask + off : nullptr;
+    tc.n = len;
+    tc.vec = vec ? 1u : 0u;
+    tc.nvec = vec ? len / (16 / es) : len;
+    hipError_t e = launch_vote_task(tc, ws, c->num_cus, s, false);
+    if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
+    HIPCHK(hipEventRecord(c->mem_consumed[j], s));
+  }
+  return FTV_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -451,12 +486,6 @@ int ftv_vote(ftv_ctx *c, const ftv_vote_desc *desc, void *stream) {
   return FTV_OK;
 }
 
-}  // extern "C"
-namespace {
-int mem_pieces(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, const TaskD &t, const VoteWs &ws,
-               bool vec, uint64_t es, uint64_t chunk, uint64_t set_bytes, uint32_t nhost, hipStream_t s);
-}  // namespace
-extern "C" {
 
 int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, uint64_t chunk_bytes,
                  void *stream) {
@@ -525,44 +554,6 @@ int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, u
   return FTV_OK;
 }
 
-}  // extern "C"
-namespace {
-// The pieces of an ftv_vote_mem call: copy, vote without finalizing.
-int mem_pieces(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, const TaskD &t, const VoteWs &ws,
-               bool vec, uint64_t es, uint64_t chunk, uint64_t set_bytes, uint32_t nhost, hipStream_t s) {
-  const uint64_t n = desc->n;
-  for (uint64_t off = 0, i = 0; off < n; off += chunk, ++i) {
-    const int j = (int)(i & 1);
-    const uint64_t len = std::min<uint64_t>(chunk, n - off);
-    if (i >= 2) HIPCHK(hipStreamWaitEvent(c->copy_stream, c->mem_consumed[j], 0));
-    char *set = c->stage + (uint64_t)j * set_bytes;
-    TaskD tc = t;
-    uint32_t h = 0;
-    for (uint32_t r = 0; r < desc->k; ++r) {
-      const char *src = reinterpret_cast<const char *>(desc->replicas[r]) + off * es;
-      if (memory[r] == FTV_MEM_HOST) {
-        char *dst = set + (uint64_t)h++ * (set_bytes / nhost);
-        HIPCHK(hipMemcpyAsync(dst, src, len * es, hipMemcpyHostToDevice, c->copy_stream));
-        tc.rep[r] = dst;
-      } else {
-        tc.rep[r] = src;
-      }
-    }
-    HIPCHK(hipEventRecord(c->mem_copied[j], c->copy_stream));
-    HIPCHK(hipStreamWaitEvent(s, c->mem_copied[j], 0));
-    tc.cons = desc->consensus ? reinterpret_cast<char *>(desc->consensus) + off * es : nullptr;
-    tc.mask = desc->mask ? desc->mask + off : nullptr;
-    tc.n = len;
-    tc.vec = vec ? 1u : 0u;
-    tc.nvec = vec ? len / (16 / es) : len;
-    hipError_t e = launch_vote_task(tc, ws, c->num_cus, s, false);
-    if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
-    HIPCHK(hipEventRecord(c->mem_consumed[j], s));
-  }
-  return FTV_OK;
-}
-}  // namespace
-extern "C" {
 
 int ftv_vote_batch(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, void *stream) {
   if (!c) return fail(FTV_E_INVALID, "NULL context");
