@@ -197,9 +197,10 @@ int ftv_batch_get_config(ftv_ctx *ctx, ftv_batch_cfg *out);
 int ftv_batch_set_config(ftv_ctx *ctx, const ftv_batch_cfg *cfg);
 /* Autotuner: coordinate descent from the context's current schedule over tile
  * size, block size, grid multiple, order and store kind, two passes, each
- * candidate timed on this batch (fastest of `iters` runs after a warm one, on
- * `stream`, synchronising it); the winner is re-timed against the starting
- * schedule and the faster one is installed in the context and written to
+ * candidate timed on this batch (the mean of `iters` back-to-back runs after a
+ * warm one, on `stream`, synchronising it); the winner is re-timed against the
+ * starting schedule (interleaved, twice) and the faster one is installed in
+ * the context and written to
  * *best (may be NULL).  The batch's outputs hold a valid result
  * afterwards.  If the environment variable FTV_TUNE_CACHE names a file, the
  * choice is stored there as JSON keyed by device name, CU count and a coarse
