@@ -30,6 +30,7 @@ METRIC = "replica GB/s voted on 1 MI355X and % of HBM peak; batched vs per-task;
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote_task.hpp", "paper_1405_2912_amd/csrc/ftv_vote_f32.hip",
                   "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
+BATCH_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote_batch.hip", "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
 
 
 def log(*a):
@@ -44,9 +45,10 @@ def kernel_hash(paths=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name: str, launches_bytes_alg: float):
+def traffic_from_profile(name: str, launches_bytes_alg: float, sources=None):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
+    sources = KERNEL_SOURCES if sources is None else sources
     path = os.path.join(PROFILE_DIR, name)
     if not os.path.exists(path):
         return None
@@ -54,27 +56,67 @@ def traffic_from_profile(name: str, launches_bytes_alg: float):
         d = json.load(f)
     # counters taken on other sources (a renamed or split file) or on an older
     # revision of them do not describe the kernel that runs now
-    if d.get("sources") != KERNEL_SOURCES:
+    if d.get("sources") != sources:
         return None
-    if d.get("kernel_hash") != kernel_hash(KERNEL_SOURCES):
+    if d.get("kernel_hash") != kernel_hash(sources):
         return None
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(reps_dev, sample_elems: int):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(reps_dev, single_elems: int, runs: int = 3):
+    """The oracle on the host: the OpenMP leg (the oracle's element loop split
+    over all usable cores) on the whole task, and the sequential leg on its first
+    single_elems elements; median of `runs` wall times each, input copies
+    excluded."""
     import numpy as np
     import oracle
-    reps = [r[:sample_elems].cpu().numpy() for r in reps_dev]
-    t0 = time.perf_counter()
-    oracle.vote(reps, oracle.ulp(4))
-    dt = time.perf_counter() - t0
-    bytes_rep = 3 * sample_elems * 4
-    return {"value": round(bytes_rep / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_elems} elements (2^{int(np.log2(sample_elems))}) of the same "
-                      f"3 replicas, single-threaded C oracle, {dt:.1f} s"}
+    reps = [r.cpu().numpy() for r in reps_dev]
+    n = reps[0].size
+    tol = oracle.ulp(4)
+
+    def median_s(fn):
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2]
+
+    used = [0]
+
+    def par():
+        used[0] = oracle.vote_threads(reps, tol)[1]
+    t_all = median_s(par)
+    head = [r[:single_elems] for r in reps]
+    t_one = median_s(lambda: oracle.vote(head, tol))
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    all_gbs = 3 * n * 4 / t_all / 1e9
+    one_gbs = 3 * single_elems * 4 / t_one / 1e9
+    return {"value": round(all_gbs, 4), "unit": "GB/s", "cores": used[0], "kind": "oracle",
+            "sample": f"the whole task (3 x {n} fp32, 4 ULP) on {used[0]} OpenMP threads, median of {runs} "
+                      f"runs ({t_all:.2f} s each); input copies excluded",
+            "single_thread": {"value": round(one_gbs, 4), "unit": "GB/s", "cores": 1,
+                              "sample": f"first {single_elems} elements (2^{int(np.log2(single_elems))}) of "
+                                        f"the same replicas, sequential oracle, median of {runs} runs "
+                                        f"({t_one:.2f} s each)"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "usable_cores": usable}
 
 
 def main_vote(ftv, ctx, steps, warmup, side):
+    """The timed steps, with kernel timing on: per step the vote kernel's own
+    time (HIP events on the launch stream, recorded by the library around the
+    kernel) and the whole call's time (events around the call)."""
     import torch
     import synth.device as sd
     n = side * side
@@ -89,6 +131,7 @@ def main_vote(ftv, ctx, steps, warmup, side):
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     log(f"bench: timing {steps} steps")
+    ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -97,11 +140,14 @@ def main_vote(ftv, ctx, steps, warmup, side):
         ev[i][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    kern = ctx.kernel_times()
+    ctx.set_timing(False)
+    call_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
     s = ftv.read_stats(st)
     replica_bytes = 3 * n * 4
     alg_bytes = replica_bytes + n * 4 + n          # reads + consensus + mask
-    return {"reps": reps, "wall": wall, "kern_ms": kern_ms, "replica_bytes": replica_bytes,
+    return {"reps": reps, "wall": wall, "kern_ms": sum(kern) / len(kern), "kern_min_ms": min(kern),
+            "kern_max_ms": max(kern), "call_ms": call_ms, "replica_bytes": replica_bytes,
             "alg_bytes": alg_bytes, "stats": s, "n": n}
 
 
@@ -220,7 +266,7 @@ def make_uneven_tasks(ftv, ntasks: int, seed: int, max_bytes: int = 64 << 20):
             pos, bits = synth.flip_plan(n, min(nflip, n), 8 * es[dt], seed + i, 7)
             sd.flip_bits(reps[victim], pos, bits)
         tol = ftv.exact() if dt == "i32" else (ftv.ulp(4) if dt == "f32" else ftv.ulp(2))
-        tasks.append(dict(reps=reps, n=n, k=k, dt=dt, tol=tol))
+        tasks.append(dict(reps=reps, n=n, k=k, dt=dt, tol=tol, faulty=i in faulty))
     sizes_info = dict(rep_bytes=sum(int(sizes[i]) * int(ks[i]) for i in range(ntasks)),
                       cons_bytes=int(sizes.sum()),
                       mask_bytes=int(sum(int(sizes[i]) // es[dts[i]] for i in range(ntasks))))
@@ -249,6 +295,42 @@ def output_set(ftv, tasks, out_sizes):
     return cons, mask, stats, descs
 
 
+def batch_sample(tasks, n_small, n_large, n_faulty, n_random, seed):
+    """Indices of tasks to check against the oracle: the n_small smallest, the
+    n_large largest, n_faulty of the tasks given faults, n_random others."""
+    import numpy as np
+    order = np.argsort([t["n"] for t in tasks], kind="stable")
+    faulty = [i for i, t in enumerate(tasks) if t["faulty"]]
+    rng = np.random.default_rng(seed)
+    pick = set(order[:n_small].tolist()) | set(order[len(order) - n_large:].tolist())
+    pick |= set(faulty[:n_faulty])
+    pick |= set(rng.choice(len(tasks), n_random, replace=False).tolist())
+    return sorted(int(i) for i in pick)
+
+
+def check_batch_task(ftv, tasks, descs, cons, mask, stats, i) -> bool:
+    """Task i of a batched launch against the oracle on the whole task:
+    consensus bytes, mask bytes, every count, verdict and winner."""
+    import numpy as np
+    import oracle
+    t = tasks[i]
+    host = [r.cpu().numpy() for r in t["reps"]]
+    otol = oracle.exact() if t["dt"] == "i32" else oracle.ulp(t["tol"].max_ulp)
+    ref, _ = oracle.vote_threads(host, otol)
+    d = descs[i]
+    es = host[0].itemsize
+    co = d.consensus - cons.data_ptr()
+    mo = d.mask - mask.data_ptr()
+    got_c = cons[co:co + t["n"] * es].cpu().numpy()
+    got_m = mask[mo:mo + t["n"]].cpu().numpy()
+    s = ftv.read_stats(stats, i)
+    k = t["k"]
+    return bool(np.array_equal(got_c, ref.consensus.view(np.uint8)) and np.array_equal(got_m, ref.mask)
+                and np.array_equal(s["pair"][:k, :k], ref.pair) and np.array_equal(s["disagree"][:k], ref.disagree)
+                and (s["no_majority"], s["verdict"], s["winner"], s["n"]) ==
+                (ref.no_majority, ref.verdict, ref.winner, t["n"]))
+
+
 def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10):
     import ctypes
     import numpy as np
@@ -270,6 +352,13 @@ def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10):
         ftv.vote_batch(ctx, descs_b)
     torch.cuda.synchronize()
     batched_ms = (time.perf_counter() - t0) / reps_timed * 1e3
+    # the persistent kernel alone at the tuned schedule (HIP events around it)
+    ctx.set_timing(True)
+    for _ in range(reps_timed):
+        ftv.vote_batch(ctx, descs_b)
+    kern = ctx.kernel_times()
+    ctx.set_timing(False)
+    kern_ms = sum(kern) / len(kern)
     log("bench: timing per-task launches")
     L = ftv.load()
     h = ctx.handle
@@ -286,30 +375,23 @@ def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10):
     torch.cuda.synchronize()
     per_task_ms = (time.perf_counter() - t0) / pt_rounds * 1e3
     equal = bool(torch.equal(cons_b, cons_p) and torch.equal(mask_b, mask_p) and torch.equal(st_b, st_p))
-    # oracle on a sample of tasks (smallest ones + a few random)
-    order = np.argsort([t["n"] for t in tasks])
-    sample = list(order[:12]) + list(np.random.default_rng(1).choice(len(tasks), 4, replace=False))
-    ok = 0
-    for i in sample:
-        t = tasks[int(i)]
-        if t["n"] > (1 << 22):
-            continue
-        host = [r.cpu().numpy() for r in t["reps"]]
-        otol = oracle.exact() if t["dt"] == "i32" else oracle.ulp(t["tol"].max_ulp)
-        ref = oracle.vote(host, otol)
-        s = ftv.read_stats(st_b, int(i))
-        d = descs_b[int(i)]
-        es = host[0].itemsize
-        c = cons_b[(d.consensus - cons_b.data_ptr()):(d.consensus - cons_b.data_ptr()) + t["n"] * es].cpu().numpy()
-        m = mask_b[(d.mask - mask_b.data_ptr()):(d.mask - mask_b.data_ptr()) + t["n"]].cpu().numpy()
-        good = (np.array_equal(c, ref.consensus.view(np.uint8)) and np.array_equal(m, ref.mask)
-                and s["verdict"] == ref.verdict and s["no_majority"] == ref.no_majority)
-        ok += int(good)
+    # the oracle on a sample: the smallest tasks, the two largest, some faulty
+    # ones and a few random ones, each whole
+    sample = batch_sample(tasks, n_small=12, n_large=2, n_faulty=6, n_random=4, seed=1)
+    log(f"bench: oracle check of {len(sample)} batched tasks")
+    ok = sum(check_batch_task(ftv, tasks, descs_b, cons_b, mask_b, st_b, i) for i in sample)
     alg = info["rep_bytes"] + info["cons_bytes"] + info["mask_bytes"]
     res = {"workload": f"{ntasks} tasks, bytes per replica log-uniform [1 KiB, 64 MiB], fp32/fp64/i32 "
                        f"50/30/20%, k in {{2,3,5}} 20/60/20%, 1% faulty tasks",
            "replica_bytes": info["rep_bytes"], "alg_bytes": alg,
            "batched_ms": round(batched_ms, 3), "per_task_ms": round(per_task_ms, 3),
+           "roofline": {"bound": "hbm", "achieved": round(alg / kern_ms / 1e6, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(alg / kern_ms / 1e6 / HBM_PEAK_GBS, 4),
+                        "traffic": traffic_from_profile("vote_batch_4096_uneven_counters.json", alg,
+                                                        BATCH_SOURCES),
+                        "kernel": "k_vote_batch (tuned schedule)", "alg_bytes_per_launch": alg,
+                        "kernel_ms": round(kern_ms, 4), "kernel_ms_min": round(min(kern), 4),
+                        "kernel_ms_max": round(max(kern), 4), "launches": len(kern)},
            "speedup": round(per_task_ms / batched_ms, 3),
            "batched_replica_gbps": round(info["rep_bytes"] / batched_ms / 1e6, 1),
            "batched_hbm_frac": round(alg / batched_ms / 1e6 / HBM_PEAK_GBS, 4),
@@ -532,7 +614,8 @@ def bench_redundant(ftv, ctx, side=16384, calls=7):
 # ---------------------------------------------------------------------------
 # serving: Poisson arrivals, continuous batching, p50/p99 latency
 # ---------------------------------------------------------------------------
-def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int = 128, count: int = None):
+def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int = 128, count: int = None,
+                  n_span: int = 0, n_rand: int = 0):
     """chunk_mib: bytes per replica a request advances per iteration.  On
     MI355X, 32 / 64 / 128 / 256 MiB gave p99 593 / 496 / 373 / 338 us at the
     same p50 (97 us); 128 MiB keeps more iterations shared between requests."""
@@ -542,6 +625,7 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
     pool_elems = (256 << 20) // 4
     log("bench: serving pool (3 x 256 MiB fp32 replicas with the large-task faults)")
     pool = sd.large_task_set(pool_elems, "f32", flip_rate=1e-7 * 64)
+    torch.cuda.synchronize()
     srv = ftv.Server(hbm_budget_bytes=64 << 30, arena_bytes=24 << 30, chunk_bytes=chunk_mib << 20,
                      max_slots=1024, max_queue=1 << 20)
     rng = np.random.default_rng(14052912 + 4)
@@ -550,6 +634,13 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
     sizes = np.floor(np.exp(rng.uniform(np.log(4096), np.log(256 << 20), count)) / 4).astype(np.int64)
     offs = [int(rng.integers(0, (pool_elems - int(n)) // 64 + 1)) * 64 for n in sizes]
     tol = ftv.ulp(4)
+    # requests read back and checked against the oracle: the first n_span ones
+    # that span at least three iterations, and n_rand others at random; they
+    # get outputs of their own and are released only after the check
+    big = [i for i in range(count) if int(sizes[i]) * 4 > 2 * (chunk_mib << 20)][:n_span]
+    rest = [i for i in range(count) if i not in set(big)]
+    pick = set(big) | set(np.random.default_rng(5).choice(rest, min(n_rand, len(rest)), replace=False).tolist())
+    held = {}
     log(f"bench: serving {count} requests at {rate:.0f}/s")
     t0 = ftv.now_ns() + 5_000_000
     arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
@@ -568,7 +659,12 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
                 time.sleep(0.0001)
         n, o = int(sizes[i]), offs[i]
         reps = [p[o:o + n] for p in pool]
-        outstanding.append(srv.submit_vote(reps, tol, t_arrival_ns=ta, n=n))
+        if i in pick:
+            c = torch.empty(n, dtype=torch.float32, device="cuda")
+            m = torch.empty(n, dtype=torch.uint8, device="cuda")
+            held[i] = (srv.submit_vote(reps, tol, c, m, t_arrival_ns=ta, n=n, inputs_ready=True), c, m)
+            continue
+        outstanding.append(srv.submit_vote(reps, tol, t_arrival_ns=ta, n=n, inputs_ready=True))
         max_out = max(max_out, len(outstanding))
         if len(outstanding) > 64 and srv.poll(outstanding[0], 0) is not None:
             srv.release(outstanding.pop(0))
@@ -576,8 +672,28 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
         srv.poll(tk, -1)
         srv.release(tk)
     st = srv.stats()
+    checked = ok = 0
+    if held:
+        import oracle
+        log(f"bench: oracle check of {len(held)} served requests")
+        host_pool = [p.cpu().numpy() for p in pool]
+        for i, (tk, c, m) in sorted(held.items()):
+            res = srv.poll(tk, -1)
+            n, o = int(sizes[i]), offs[i]
+            ref, _ = oracle.vote_threads([hp[o:o + n] for hp in host_pool], oracle.ulp(4))
+            s = ftv.result_stats(res)
+            good = (res.status == 0 and np.array_equal(c.cpu().numpy().view(np.uint32), ref.consensus.view(np.uint32))
+                    and np.array_equal(m.cpu().numpy(), ref.mask) and np.array_equal(s["pair"][:3, :3], ref.pair)
+                    and np.array_equal(s["disagree"][:3], ref.disagree)
+                    and (s["no_majority"], s["verdict"], s["winner"], s["n"]) ==
+                    (ref.no_majority, ref.verdict, ref.winner, n))
+            checked += 1
+            ok += int(good)
+            srv.release(tk)
+        del host_pool
+    largest = max((int(sizes[i]) for i in held), default=0)
     srv.close()
-    del pool
+    del pool, held
     torch.cuda.empty_cache()
     return {"workload": f"Poisson {rate:.0f} req/s, {count} requests, sizes log-uniform [4 KiB, 256 MiB] per "
                         f"replica, k=3 fp32, budget 64 GiB, {chunk_mib} MiB per replica per iteration",
@@ -589,7 +705,9 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
             "shared_iterations": int(st["shared_iterations"]),
             "max_requests_per_iteration": int(st["max_requests_per_iteration"]),
             "served_replica_gbps": round(st["replica_gbps"], 2),
-            "peak_bytes_in_flight": int(st["peak_bytes_in_flight"])}
+            "peak_bytes_in_flight": int(st["peak_bytes_in_flight"]),
+            "oracle_sampled_ok": f"{ok}/{checked}" if checked else None,
+            "oracle_sampled_largest_elems": largest if checked else None}
 
 
 def bench_serving_ramp(ftv, ctx, seconds: float = 2.0):
@@ -613,7 +731,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--side", type=int, default=16384)
     ap.add_argument("--main-only", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=27)
+    ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -651,6 +769,7 @@ def main():
     value = m["replica_bytes"] / (ms_per_step / 1e3) / 1e9
     achieved = m["alg_bytes"] / (m["kern_ms"] / 1e3) / 1e9
     traffic = traffic_from_profile("vote_f32_k3_16384sq_counters.json", m["alg_bytes"])
+    call_frac = m["alg_bytes"] / (m["call_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -672,7 +791,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_vote_task<f32, ULP, k=3, vector>",
-                     "alg_bytes_per_launch": m["alg_bytes"], "kernel_ms": round(m["kern_ms"], 4)},
+                     "alg_bytes_per_launch": m["alg_bytes"], "kernel_ms": round(m["kern_ms"], 4),
+                     "kernel_ms_min": round(m["kern_min_ms"], 4), "kernel_ms_max": round(m["kern_max_ms"], 4),
+                     "call_ms": round(m["call_ms"], 4), "call_frac": round(call_frac, 4)},
         "verdict": m["stats"]["verdict"],
     }
     log("bench: CPU oracle baseline")
@@ -687,7 +808,7 @@ def main():
         out["siblings"] = bench_siblings(ftv)
         out["redundant"] = bench_redundant(ftv, ctx)
         out["mixed_memory"] = bench_mixed(ftv, ctx)
-        out["serving"] = bench_serving(ftv, ctx, args.serve_seconds)
+        out["serving"] = bench_serving(ftv, ctx, args.serve_seconds, n_span=4, n_rand=12)
         out["serving_ramp"] = bench_serving_ramp(ftv, ctx, min(2.0, args.serve_seconds))
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -23,10 +23,13 @@
  *  - Return value: FTV_OK (0) or a negative FTV_E_* code.  No call throws or
  *    aborts.  ftv_last_error() returns a thread-local description of the last
  *    failure on the calling thread.
- *  - A context is used by one host thread at a time, and calls that share a
- *    context must be ordered on one stream (they share its workspace).  The
- *    server calls (ftv_submit / ftv_poll / ftv_release / ftv_server_get_stats) are
- *    thread-safe.
+ *  - A context is used by one host thread at a time.  Its calls may be issued
+ *    on different streams: per-task and block votes count in accumulators of
+ *    their stream's own (at most 64 streams per context, FTV_E_BUSY beyond),
+ *    and a batched or mixed-memory call on another stream than the previous
+ *    one of its kind is ordered after that one on the device (they share the
+ *    context's tables and staging).  The server calls (ftv_submit / ftv_poll /
+ *    ftv_release / ftv_server_get_stats) are thread-safe.
  */
 #ifndef FTV_H
 #define FTV_H
@@ -45,7 +48,7 @@ extern "C" {
 #define FTV_E_ALIGN (-4)    /* pointer misaligned for the requested call */
 #define FTV_E_HIP (-5)      /* a HIP runtime call failed (text in ftv_last_error) */
 #define FTV_E_NOMEM (-6)    /* allocation failed, or request exceeds the budget */
-#define FTV_E_BUSY (-7)     /* server queue full */
+#define FTV_E_BUSY (-7)     /* server queue full; context stream slots exhausted */
 #define FTV_E_NOTREADY (-8) /* ftv_poll: request still in flight */
 #define FTV_E_CLOSED (-9)   /* server shutting down / unknown ticket */
 
@@ -123,7 +126,8 @@ int64_t ftv_now_ns(void);
 /* Create a context on HIP device `device`: allocates its workspace (a few MiB).
  * *out receives the handle.  Errors: FTV_E_INVALID, FTV_E_HIP, FTV_E_NOMEM. */
 int ftv_ctx_create(int device, ftv_ctx **out);
-/* Waits for nothing: the caller must synchronise its streams first. */
+/* Synchronises the device (work still queued may read the workspace), then
+ * frees the context and its workspace. */
 int ftv_ctx_destroy(ftv_ctx *ctx);
 
 /* ftv_vote -- the element-wise majority vote of one task (Sec. IV-D).
@@ -140,8 +144,26 @@ int ftv_ctx_destroy(ftv_ctx *ctx);
  * schedule changes them.
  * Errors: FTV_E_INVALID (NULL replica/stats, reserved != 0, bad tolerance),
  * FTV_E_DTYPE, FTV_E_K, FTV_E_ALIGN (pointer not a multiple of the element
- * size; stats not 8-byte aligned), FTV_E_HIP. */
+ * size; stats not 8-byte aligned), FTV_E_BUSY (a 65th stream on the context),
+ * FTV_E_HIP. */
 int ftv_vote(ftv_ctx *ctx, const ftv_vote_desc *desc, void *stream);
+
+/* Kernel timing, the measurement of the paper's voter comparison (Sec. V-A
+ * times the voter kernels alone, per data size, transfers excluded).  With
+ * timing on (on = 1), each ftv_vote records a pair of HIP events on its stream
+ * around its vote kernel (the finalize kernel after it is not included), and
+ * each ftv_vote_batch launches its three kernels directly instead of from the
+ * captured graph, with the events around the persistent vote kernel; the
+ * results are unchanged.  At most 1024 launches are recorded between two
+ * reads; later ones run untimed.  on = 0 stops recording.  Turning timing on
+ * creates the events once (FTV_E_HIP if that fails) and clears the record.
+ * Errors: FTV_E_INVALID. */
+int ftv_ctx_set_timing(ftv_ctx *ctx, int on);
+/* Waits for the recorded launches, writes the kernel time of the first
+ * min(cap, count) of them to ms[] (host, milliseconds, in launch order), sets
+ * *count to the number recorded, and clears the record.  Errors:
+ * FTV_E_INVALID (NULL count, NULL ms with cap > 0), FTV_E_HIP. */
+int ftv_ctx_kernel_times(ftv_ctx *ctx, float *ms, uint32_t cap, uint32_t *count);
 
 /* ftv_vote_mem -- ftv_vote over replicas that lie in different memories: a
  * task duplicated onto a CPU and a GPU leaves one result in host memory and
@@ -295,6 +317,12 @@ typedef struct ftv_request {
   uint64_t block_bytes;
   int64_t t_arrival_ns; /* ftv_now_ns() clock; 0 = time of submission */
   uint64_t user_tag;
+  void *ready;          /* hipEvent_t recorded after the work that produces the
+                           request's inputs, or NULL when they are complete at
+                           submission; the server's stream waits for it before
+                           it first reads them.  It must stay valid and must not
+                           be recorded again until ftv_poll reports the request
+                           done. */
 } ftv_request;
 
 typedef struct ftv_result {

@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc: no FMA contraction, no fast-math."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                                "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -61,8 +61,8 @@ def lib():
         L.fto_order_key.restype = u64
         L.fto_vote.argtypes = [i32, i32, u64, vp, i32, u64, dbl, dbl, vp, vp, vp, vp]
         L.fto_vote.restype = i32
-        L.fto_vote_one.argtypes = [i32, i32, vp, i32, u64, dbl, dbl, vp, vp]
-        L.fto_vote_one.restype = i32
+        L.fto_vote_threads.argtypes = [i32, i32, u64, vp, i32, u64, dbl, dbl, vp, vp, vp, vp, i32, vp]
+        L.fto_vote_threads.restype = i32
         L.fto_fnv1a_words.argtypes = [vp, u64]
         L.fto_fnv1a_words.restype = u64
         L.fto_fingerprint.argtypes = [vp, u64, u64, vp]
@@ -159,16 +159,31 @@ def vote(replicas, tol: Tol) -> VoteResult:
                       int(vw[0]), int(vw[1]))
 
 
-def vote_one(dtype, bits, tol: Tol):
-    """Vote of one element given as k raw bit patterns -> (consensus bits, mask byte)."""
-    x = np.array([int(b) for b in bits], dtype=np.uint64)
-    cons = np.zeros(1, dtype=np.uint64)
-    m = np.zeros(1, dtype=np.uint8)
-    rc = lib().fto_vote_one(dtype_code(dtype), len(x), x.ctypes.data, tol.kind, tol.max_ulp,
-                            tol.delta, tol.abs_floor, cons.ctypes.data, m.ctypes.data)
+def vote_threads(replicas, tol: Tol, nthreads: int = 0):
+    """The same vote with the element loop split over host threads (OpenMP);
+    returns (VoteResult, threads used).  nthreads = 0: OpenMP's default."""
+    reps = [np.ascontiguousarray(r) for r in replicas]
+    k = len(reps)
+    dt = reps[0].dtype
+    n = reps[0].size
+    for r in reps:
+        if r.dtype != dt or r.size != n:
+            raise ValueError("replicas must share dtype and size")
+    cons = np.empty(n, dtype=dt)
+    mask = np.empty(n, dtype=np.uint8)
+    counts = np.zeros(57, dtype=np.uint64)
+    vw = np.zeros(2, dtype=np.int32)
+    used = ctypes.c_int(0)
+    ptrs = _ptr_array(reps)
+    rc = lib().fto_vote_threads(dtype_code(dt), k, n, ctypes.cast(ptrs, ctypes.c_void_p), tol.kind,
+                                tol.max_ulp, tol.delta, tol.abs_floor, cons.ctypes.data,
+                                mask.ctypes.data, counts.ctypes.data, vw.ctypes.data, int(nthreads),
+                                ctypes.byref(used))
     if rc != 0:
         raise ValueError(f"oracle vote rejected arguments (code {rc})")
-    return int(cons[0]), int(m[0])
+    pair = counts[:49].reshape(7, 7)[:k, :k].copy()
+    return VoteResult(cons, mask, pair, counts[49:49 + k].copy(), int(counts[56]),
+                      int(vw[0]), int(vw[1])), int(used.value)
 
 
 def fnv1a_words(words) -> int:

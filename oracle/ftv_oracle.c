@@ -9,9 +9,11 @@
  * header, table or constant with the GPU library: every definition below is
  * written out again from the paper's statement of the problem.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
  * (no FMA contraction, no flush-to-zero: the relative test must round exactly
- * as IEEE-754 binary64 with round-to-nearest-even prescribes).
+ * as IEEE-754 binary64 with round-to-nearest-even prescribes).  OpenMP is only
+ * used by fto_vote_threads, the host-core timing leg; every other function is
+ * sequential.
  *
  * Everything is scalar and sequential, one element at a time, in the order the
  * definitions are stated.  Element values are handled as raw bit patterns
@@ -283,14 +285,59 @@ int fto_vote(int dt, int k, uint64_t n, const void *const *reps, int kind, uint6
   return 0;
 }
 
-/* Vote of a single element given as bit patterns (used by sampled checks). */
-int fto_vote_one(int dt, int k, const uint64_t *x, int kind, uint64_t max_ulp, double delta,
-                 double abs_floor, uint64_t *cons, uint8_t *mask) {
+/* ---- exported: the same vote on several host threads ----------------------
+ * The element loop of fto_vote with the elements split into one contiguous
+ * range per thread (OpenMP), each thread adding to counters of its own; the
+ * per-thread counters are summed afterwards (integer sums: the order does not
+ * matter) and the verdict is taken from the totals.  Consensus, mask, counts
+ * and verdict are those of fto_vote.  nthreads <= 0: OpenMP's default.
+ * *used receives the number of threads that ran. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int fto_vote_threads(int dt, int k, uint64_t n, const void *const *reps, int kind, uint64_t max_ulp,
+                     double delta, double abs_floor, void *consensus, uint8_t *mask, uint64_t *counts,
+                     int32_t *vw, int nthreads, int *used) {
   otol t = {kind, max_ulp, delta, abs_floor};
   int rc = o_check(dt, k, &t);
   if (rc) return rc;
-  uint64_t cnt[O_NCOUNT] = {0};
-  o_vote_element(dt, k, &t, x, cons, mask, cnt);
+  int T = 1;
+#ifdef _OPENMP
+  T = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+  uint64_t *per = (uint64_t *)calloc((size_t)T * O_NCOUNT, sizeof(uint64_t));
+  if (!per) return -6;
+  int ran = 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(T)
+#endif
+  {
+    int me = 0, nt = 1;
+#ifdef _OPENMP
+    me = omp_get_thread_num();
+    nt = omp_get_num_threads();
+#pragma omp single
+    ran = nt;
+#endif
+    uint64_t lo = n * (uint64_t)me / (uint64_t)nt, hi = n * (uint64_t)(me + 1) / (uint64_t)nt;
+    uint64_t *cnt = per + (size_t)me * O_NCOUNT;
+    uint64_t x[O_MAXK];
+    for (uint64_t i = lo; i < hi; ++i) {
+      for (int r = 0; r < k; ++r) x[r] = o_load(reps[r], dt, i);
+      uint64_t c;
+      uint8_t m;
+      o_vote_element(dt, k, &t, x, &c, &m, cnt);
+      if (consensus) o_store(consensus, dt, i, c);
+      if (mask) mask[i] = m;
+    }
+  }
+  for (int i = 0; i < O_NCOUNT; ++i) {
+    counts[i] = 0;
+    for (int j = 0; j < T; ++j) counts[i] += per[(size_t)j * O_NCOUNT + i];
+  }
+  free(per);
+  o_verdict(k, counts, &vw[0], &vw[1]);
+  if (used) *used = ran;
   return 0;
 }
 

@@ -100,12 +100,26 @@ int make_task(const ftv_vote_desc *d, bool strict, TaskD *out) {
 using namespace ftv;
 
 // ---------------------------------------------------------------------------
+// Count accumulators are kept per stream: calls on one stream are ordered by
+// it and share a slot; calls on different streams get different slots, so two
+// streams voting with one context can never mix their counts.  A slot holds
+// the per-task vote counters and the block-vote counters; the kernels leave
+// both zeroed.
+constexpr int kStreamSlots = 64;
+constexpr int kBlkWords = 16;
+constexpr int kSlotWords = kNumCounters + kBlkWords;
+// launches whose kernel time a context records at most between two reads
+constexpr uint32_t kMaxTimed = 1024;
+
 struct ftv_ctx {
   int device = 0;
   int num_cus = 256;
   std::string name;
-  // per-task launch workspace: count accumulators (zero between launches)
-  uint64_t *partials = nullptr;
+  // count accumulators, kStreamSlots x kSlotWords (zero between launches),
+  // and the stream each slot belongs to
+  uint64_t *slots = nullptr;
+  hipStream_t slot_stream[kStreamSlots] = {};
+  int nslots = 0;
   // batched launch
   ftv_batch_cfg cfg{};
   uint64_t cap_tasks = 0;
@@ -116,13 +130,16 @@ struct ftv_ctx {
   hipEvent_t staged{};
   bool staged_pending = false;
   hipStream_t cap_stream{};
+  // the last batched launch: later batches on another stream wait for it, and
+  // the tables are only freed once it has finished
+  hipEvent_t batch_done{};
+  hipStream_t batch_stream{};
+  bool batch_pending = false;
   hipGraphExec_t gexec{};
   hipGraph_t graph{};
   bool gvalid = false;
   uint32_t g_grid = 0;
   ftv_batch_cfg g_cfg{};
-  // block vote workspace
-  uint64_t *blk_acc = nullptr;
   // ftv_run_redundant: replicas abandoned after a timeout, freed once their
   // work has finished (ftv_run.cpp)
   RunState *run = nullptr;
@@ -133,6 +150,16 @@ struct ftv_ctx {
   hipStream_t copy_stream{};
   hipEvent_t mem_entry{}, mem_copied[2]{}, mem_consumed[2]{};
   bool mem_ready = false;
+  // the last ftv_vote_mem call: a call on another stream waits for it before
+  // it touches the staging sets
+  hipEvent_t mem_done{};
+  hipStream_t mem_stream{};
+  bool mem_pending = false;
+  // kernel timing (ftv_ctx_set_timing): a pair of events around the vote
+  // kernel of each ftv_vote and the persistent kernel of each ftv_vote_batch
+  bool timing = false;
+  hipEvent_t tev[2 * kMaxTimed] = {};
+  uint32_t ntev = 0;
 };
 
 namespace {
@@ -169,11 +196,31 @@ void free_batch(ftv_ctx *c) {
   c->cap_tasks = 0;
 }
 
+// The count slot of stream s (assigned on first use).
+int stream_slot(ftv_ctx *c, hipStream_t s, uint64_t **acc) {
+  for (int j = 0; j < c->nslots; ++j)
+    if (c->slot_stream[j] == s) {
+      *acc = c->slots + (uint64_t)j * kSlotWords;
+      return FTV_OK;
+    }
+  if (c->nslots == kStreamSlots)
+    return fail(FTV_E_BUSY, "a context keeps count accumulators for at most 64 streams");
+  c->slot_stream[c->nslots] = s;
+  *acc = c->slots + (uint64_t)c->nslots * kSlotWords;
+  ++c->nslots;
+  return FTV_OK;
+}
+
 int ensure_capacity(ftv_ctx *c, uint64_t tasks, hipStream_t s) {
   if (tasks <= c->cap_tasks) return FTV_OK;
-  // the old buffers may still be read by queued work
-  HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipDeviceSynchronize());
+  // the old buffers may still be read by the last batch, on whatever stream
+  // it was launched (the caller's stream s is ordered after it already)
+  (void)s;
+  if (c->batch_pending) HIPCHK(hipEventSynchronize(c->batch_done));
+  if (c->staged_pending) {
+    HIPCHK(hipEventSynchronize(c->staged));
+    c->staged_pending = false;
+  }
   free_batch(c);
   const uint64_t nt = std::max<uint64_t>(tasks + tasks / 2, 1024);
   const size_t tb = tab_bytes(nt);
@@ -292,6 +339,9 @@ int build_tables(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStr
 
 int batch_run(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStream_t s) {
   if (ntasks == 0) return FTV_OK;
+  // the tables, queue head and accumulators are the context's: a batch on
+  // another stream than the last one is ordered after it on the device
+  if (c->batch_pending && c->batch_stream != s) HIPCHK(hipStreamWaitEvent(s, c->batch_done, 0));
   uint64_t ntiles = 0;
   int rc = build_tables(c, descs, ntasks, s, &ntiles);
   if (rc) return rc;
@@ -301,9 +351,28 @@ int batch_run(ftv_ctx *c, const ftv_vote_desc *descs, uint64_t ntasks, hipStream
   uint32_t g = 1;
   while (g < grid) g <<= 1;
   g = (uint32_t)std::min<uint64_t>(g, (uint64_t)c->cfg.grid_mult * c->num_cus);
-  rc = ensure_graph(c, g);
-  if (rc) return rc;
-  HIPCHK(hipGraphLaunch(c->gexec, s));
+  if (c->timing && c->ntev < kMaxTimed) {
+    // timed: the graph's three kernels launched directly, with events around
+    // the persistent one (same launch parameters as the captured graph)
+    const BatchLaunch b = make_launch(c, g);
+    hipEvent_t *ev = c->tev + 2 * c->ntev;
+    hipError_t e = launch_batch_zero(b, s);
+    if (e != hipSuccess) return hip_fail(e, "zero kernel launch");
+    HIPCHK(hipEventRecord(ev[0], s));
+    e = launch_batch_vote(b, s);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    HIPCHK(hipEventRecord(ev[1], s));
+    e = launch_batch_finalize(b, s);
+    if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
+    ++c->ntev;
+  } else {
+    rc = ensure_graph(c, g);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(c->gexec, s));
+  }
+  HIPCHK(hipEventRecord(c->batch_done, s));
+  c->batch_stream = s;
+  c->batch_pending = true;
   return FTV_OK;
 }
 
@@ -430,11 +499,11 @@ int ftv_ctx_create(int device, ftv_ctx **out) {
   c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->name = prop.gcnArchName;
   c->cfg = kDefaultCfg;
-  bool ok = hipMalloc(&c->partials, sizeof(uint64_t) * kNumCounters) == hipSuccess &&
-            hipMemset(c->partials, 0, sizeof(uint64_t) * kNumCounters) == hipSuccess &&
-            hipMalloc(&c->d_queue, 256) == hipSuccess && hipMalloc(&c->blk_acc, 256) == hipSuccess &&
-            hipMemset(c->blk_acc, 0, 256) == hipSuccess &&
+  const size_t slot_bytes = sizeof(uint64_t) * kSlotWords * kStreamSlots;
+  bool ok = hipMalloc(&c->slots, slot_bytes) == hipSuccess && hipMemset(c->slots, 0, slot_bytes) == hipSuccess &&
+            hipMalloc(&c->d_queue, 256) == hipSuccess &&
             hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->batch_done, hipEventDisableTiming) == hipSuccess &&
             hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess &&
             hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
@@ -460,10 +529,11 @@ int ftv_ctx_destroy(ftv_ctx *c) {
   (void)hipDeviceSynchronize();
   free_batch(c);
   run_state_destroy(c->run);
-  if (c->partials) (void)hipFree(c->partials);
+  for (uint32_t i = 0; i < 2 * kMaxTimed && c->tev[0]; ++i) (void)hipEventDestroy(c->tev[i]);
+  if (c->slots) (void)hipFree(c->slots);
   if (c->d_queue) (void)hipFree(c->d_queue);
-  if (c->blk_acc) (void)hipFree(c->blk_acc);
   if (c->staged) (void)hipEventDestroy(c->staged);
+  if (c->batch_done) (void)hipEventDestroy(c->batch_done);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->mem_ready) {
     (void)hipEventDestroy(c->mem_entry);
@@ -471,6 +541,7 @@ int ftv_ctx_destroy(ftv_ctx *c) {
       (void)hipEventDestroy(c->mem_copied[j]);
       (void)hipEventDestroy(c->mem_consumed[j]);
     }
+    (void)hipEventDestroy(c->mem_done);
     (void)hipStreamDestroy(c->copy_stream);
   }
   if (c->stage) (void)hipFree(c->stage);
@@ -483,9 +554,51 @@ int ftv_vote(ftv_ctx *c, const ftv_vote_desc *desc, void *stream) {
   TaskD t;
   int rc = make_task(desc, false, &t);
   if (rc) return rc;
-  VoteWs ws{c->partials};
-  hipError_t e = launch_vote_task(t, ws, c->num_cus, (hipStream_t)stream);
+  VoteWs ws{nullptr};
+  rc = stream_slot(c, (hipStream_t)stream, &ws.acc);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->timing && c->ntev < kMaxTimed) {
+    hipEvent_t *ev = c->tev + 2 * c->ntev;
+    HIPCHK(hipEventRecord(ev[0], s));
+    hipError_t e = launch_vote_task(t, ws, c->num_cus, s, false);
+    if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
+    HIPCHK(hipEventRecord(ev[1], s));
+    e = launch_vote_finalize(t, ws, s);
+    if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
+    ++c->ntev;
+    return FTV_OK;
+  }
+  hipError_t e = launch_vote_task(t, ws, c->num_cus, s);
   if (e != hipSuccess) return hip_fail(e, "vote kernel launch");
+  return FTV_OK;
+}
+
+int ftv_ctx_set_timing(ftv_ctx *c, int on) {
+  if (!c || (on != 0 && on != 1)) return fail(FTV_E_INVALID, "NULL context or on not 0/1");
+  if (on && !c->tev[0]) {
+    for (uint32_t i = 0; i < 2 * kMaxTimed; ++i)
+      if (hipEventCreate(&c->tev[i]) != hipSuccess) {
+        (void)hipGetLastError();
+        for (uint32_t j = 0; j < i; ++j) (void)hipEventDestroy(c->tev[j]);
+        memset(c->tev, 0, sizeof(c->tev));
+        return fail(FTV_E_HIP, "cannot create the timing events");
+      }
+  }
+  c->timing = on != 0;
+  c->ntev = 0;
+  return FTV_OK;
+}
+
+int ftv_ctx_kernel_times(ftv_ctx *c, float *ms, uint32_t cap, uint32_t *count) {
+  if (!c || !count || (cap && !ms)) return fail(FTV_E_INVALID, "NULL argument");
+  const uint32_t n = std::min(c->ntev, cap);
+  for (uint32_t i = 0; i < n; ++i) {
+    HIPCHK(hipEventSynchronize(c->tev[2 * i + 1]));
+    HIPCHK(hipEventElapsedTime(&ms[i], c->tev[2 * i], c->tev[2 * i + 1]));
+  }
+  *count = c->ntev;
+  c->ntev = 0;
   return FTV_OK;
 }
 
@@ -518,7 +631,8 @@ int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, u
   hipStream_t s = (hipStream_t)stream;
   if (!c->mem_ready) {
     bool ok = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreateWithFlags(&c->mem_entry, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&c->mem_entry, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->mem_done, hipEventDisableTiming) == hipSuccess;
     for (int j = 0; j < 2; ++j)
       ok = ok && hipEventCreateWithFlags(&c->mem_copied[j], hipEventDisableTiming) == hipSuccess &&
            hipEventCreateWithFlags(&c->mem_consumed[j], hipEventDisableTiming) == hipSuccess;
@@ -528,6 +642,12 @@ int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, u
     }
     c->mem_ready = true;
   }
+  VoteWs ws{nullptr};
+  rc = stream_slot(c, s, &ws.acc);
+  if (rc) return rc;
+  // the staging sets are the context's: a call on another stream than the
+  // last one is ordered after it on the device
+  if (c->mem_pending && c->mem_stream != s) HIPCHK(hipStreamWaitEvent(s, c->mem_done, 0));
   if (c->stage_bytes < 2 * set_bytes) {
     HIPCHK(hipStreamSynchronize(s));  // the old staging may still be read
     HIPCHK(hipStreamSynchronize(c->copy_stream));
@@ -541,7 +661,6 @@ int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, u
     }
     c->stage_bytes = 2 * set_bytes;
   }
-  VoteWs ws{c->partials};
   // copies into a staging set wait for the votes that last read it: the
   // previous calls' (this entry event) and the piece two before
   HIPCHK(hipEventRecord(c->mem_entry, s));
@@ -549,11 +668,14 @@ int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, u
   rc = mem_pieces(c, desc, memory, t, ws, vec, es, chunk, set_bytes, nhost, s);
   if (rc != FTV_OK) {
     // leave the accumulators zeroed for the next call
-    (void)hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * kNumCounters, s);
+    (void)hipMemsetAsync(ws.acc, 0, sizeof(uint64_t) * kNumCounters, s);
     return rc;
   }
   hipError_t e = launch_vote_finalize(t, ws, s);
   if (e != hipSuccess) return hip_fail(e, "finalize kernel launch");
+  HIPCHK(hipEventRecord(c->mem_done, s));
+  c->mem_stream = s;
+  c->mem_pending = true;
   return FTV_OK;
 }
 
@@ -740,7 +862,10 @@ int ftv_vote_blocks(ftv_ctx *c, const void *const *replicas, uint32_t k, int32_t
   b.cons = consensus;
   b.mask = mask;
   b.bstats = bstats;
-  b.acc = c->blk_acc;
+  uint64_t *slot = nullptr;
+  rc = stream_slot(c, (hipStream_t)stream, &slot);
+  if (rc) return rc;
+  b.acc = slot + kNumCounters;
   hipError_t e = launch_vote_blocks(b, c->num_cus, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "block vote kernel launch");
   return FTV_OK;

@@ -112,6 +112,7 @@ struct Req {
   bool own_cons = false, own_mask = false, own_fps = false;
   uint64_t cons_bytes = 0, mask_bytes = 0;
   int status = FTV_OK;
+  bool admitted = false;  // its bytes count against the budget
   ftv_stats stats{};
 };
 
@@ -228,6 +229,7 @@ void admit(ftv_server *s) {
     }
     r.state = Q_ACTIVE;
     r.t_admit = now;
+    r.admitted = true;
     s->bytes_in_flight += r.in_bytes + r.out_bytes;
     s->peak_bytes = std::max(s->peak_bytes, s->bytes_in_flight);
     note_queue(s, now);
@@ -250,6 +252,8 @@ int launch_iteration(ftv_server *s, Iter &it) {
   for (uint64_t tk : s->active) {
     Req &r = s->reqs[tk];
     if (r.new_slot) {
+      // the work that produces the request's replicas comes first
+      if (r.rq.ready) HIPCHK(hipStreamWaitEvent(s->stream, (hipEvent_t)r.rq.ready, 0));
       hs[nnew++] = (uint32_t)r.slot;
       HIPCHK(hipMemcpyAsync(s->d_tasks + r.slot, s->h_tasks + r.slot, sizeof(TaskD),
                             hipMemcpyHostToDevice, s->stream));
@@ -301,6 +305,7 @@ int launch_iteration(ftv_server *s, Iter &it) {
   HIPCHK(launch_slots_finalize(s->d_tasks, s->d_acc, d_fin, (uint32_t)nfin, s->stream));
   for (uint64_t tk : s->fp_wait) {
     Req &r = s->reqs[tk];
+    if (r.rq.ready) HIPCHK(hipStreamWaitEvent(s->stream, (hipEvent_t)r.rq.ready, 0));
     if (r.rq.fp_bytes)
       HIPCHK(launch_fingerprint(r.rq.fp_buf, r.rq.fp_bytes, r.rq.block_bytes, r.fps, s->stream));
     it.finishing.push_back(tk);
@@ -586,7 +591,10 @@ int ftv_release(ftv_server *s, uint64_t ticket) {
   Req &r = it->second;
   if (r.state != Q_DONE) return fail(FTV_E_NOTREADY, "request still in flight");
   free_outputs(s, r);
-  s->bytes_in_flight -= r.out_bytes;
+  // a completed request still counts its server-owned outputs (its inputs
+  // left the budget at completion); one ended by a failure before completing
+  // still counts all it was admitted with; one never admitted counts nothing
+  if (r.admitted) s->bytes_in_flight -= r.in_bytes + r.out_bytes;
   s->reqs.erase(it);
   s->cv_work.notify_one();
   return FTV_OK;

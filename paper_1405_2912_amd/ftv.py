@@ -69,7 +69,7 @@ class ServerCfg(Structure):
 class Request(Structure):
     _fields_ = [("kind", c_int32), ("reserved", c_uint32), ("vote", VoteDesc),
                 ("fp_buf", c_void_p), ("fp_bytes", c_uint64), ("block_bytes", c_uint64),
-                ("t_arrival_ns", c_int64), ("user_tag", c_uint64)]
+                ("t_arrival_ns", c_int64), ("user_tag", c_uint64), ("ready", c_void_p)]
 
 
 class Result(Structure):
@@ -128,7 +128,8 @@ EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv
            "ftv_submit", "ftv_poll", "ftv_release", "ftv_server_get_stats",
            "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote",
            "ftv_mm_create", "ftv_mm_destroy", "ftv_mm_register", "ftv_mm_request", "ftv_mm_release",
-           "ftv_mm_siblings", "ftv_mm_check", "ftv_run_redundant", "ftv_vote_mem"]
+           "ftv_mm_siblings", "ftv_mm_check", "ftv_run_redundant", "ftv_vote_mem",
+           "ftv_ctx_set_timing", "ftv_ctx_kernel_times"]
 
 _lib = None
 
@@ -156,6 +157,8 @@ def load():
     L.ftv_ctx_create.argtypes = [c_int, POINTER(vp)]
     L.ftv_ctx_destroy.argtypes = [vp]
     L.ftv_vote.argtypes = [vp, POINTER(VoteDesc), vp]
+    L.ftv_ctx_set_timing.argtypes = [vp, c_int]
+    L.ftv_ctx_kernel_times.argtypes = [vp, POINTER(ctypes.c_float), c_uint32, POINTER(c_uint32)]
     L.ftv_vote_batch.argtypes = [vp, POINTER(VoteDesc), c_uint64, vp]
     L.ftv_vote_mem.argtypes = [vp, POINTER(VoteDesc), POINTER(ctypes.c_int32), c_uint64, vp]
     L.ftv_batch_get_config.argtypes = [vp, POINTER(BatchCfg)]
@@ -272,6 +275,18 @@ class Context:
         except Exception:
             pass
 
+    # -- kernel timing -----------------------------------------------------------
+    def set_timing(self, on: bool):
+        _check(load().ftv_ctx_set_timing(self.handle, int(bool(on))))
+
+    def kernel_times(self):
+        """Kernel times (ms) of the launches recorded since timing was turned
+        on or last read, in launch order; clears the record."""
+        n = c_uint32()
+        buf = (ctypes.c_float * 1024)()
+        _check(load().ftv_ctx_kernel_times(self.handle, buf, 1024, ctypes.byref(n)))
+        return [float(x) for x in buf[:min(n.value, 1024)]]
+
     # -- batch schedule ---------------------------------------------------------
     def get_batch_config(self) -> BatchCfg:
         c = BatchCfg()
@@ -282,17 +297,72 @@ class Context:
         _check(load().ftv_batch_set_config(self.handle, ctypes.byref(cfg)))
 
 
-def make_desc(replicas, tol: Tol, consensus=None, mask=None, stats=None, n=None) -> VoteDesc:
+# ---- argument checks ---------------------------------------------------------
+# The C ABI sees only pointers, so this is the one place where a tensor's
+# device, type and size can be checked: a short replica, a small output or a
+# host tensor passed as device memory would otherwise become an out-of-bounds
+# or host-pointer access inside a kernel.  Every public call checks its
+# tensors before it allocates anything or calls the library.
+def _bad(msg: str):
+    raise ValueError(msg)
+
+
+def _check_tensor(t, name: str, *, device=None, dtype=None, min_numel: int = 0, host_ok: bool = False,
+                  min_bytes: int = 0):
+    if not t.is_contiguous():
+        _bad(f"{name} must be a contiguous tensor")
+    if not t.is_cuda and not host_ok:
+        _bad(f"{name} must be a CUDA (device) tensor")
+    if device is not None and t.is_cuda and t.device != device:
+        _bad(f"{name} is on {t.device}, expected {device}")
+    if dtype is not None and t.dtype != dtype:
+        _bad(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if t.numel() < min_numel:
+        _bad(f"{name} has {t.numel()} elements, needs at least {min_numel}")
+    if t.numel() * t.element_size() < min_bytes:
+        _bad(f"{name} has {t.numel() * t.element_size()} bytes, needs at least {min_bytes}")
+
+
+def _check_replicas(replicas, n=None, host_ok: bool = False):
+    """Replicas share one dtype, are device tensors (or host ones where the call
+    takes them) on one device, and hold at least n elements each.  Returns
+    (n, device of the device replicas or None)."""
+    if len(replicas) == 0:
+        _bad("no replicas")
+    if len(replicas) > MAX_K:
+        _bad(f"at most {MAX_K} replicas")
+    x0 = replicas[0]
+    n = int(x0.numel() if n is None else n)
+    if n < 0:
+        _bad("n must be >= 0")
+    dev = next((r.device for r in replicas if r.is_cuda), None)
+    for r, t in enumerate(replicas):
+        _check_tensor(t, f"replica {r}", device=dev, dtype=x0.dtype, min_numel=n, host_ok=host_ok)
+    return n, dev
+
+
+def _check_outputs(n: int, dtype, device, consensus=None, mask=None, stats=None):
+    import torch
+    if consensus is not None:
+        _check_tensor(consensus, "consensus", device=device, dtype=dtype, min_numel=n)
+    if mask is not None:
+        _check_tensor(mask, "mask", device=device, dtype=torch.uint8, min_numel=n)
+    if stats is not None:
+        _check_tensor(stats, "stats", device=device, min_bytes=ctypes.sizeof(Stats))
+
+
+def make_desc(replicas, tol: Tol, consensus=None, mask=None, stats=None, n=None, host_ok: bool = False) -> VoteDesc:
+    """A checked vote descriptor (see the argument checks above)."""
+    n, dev = _check_replicas(replicas, n, host_ok)
+    if dev is None and (consensus is not None or mask is not None or stats is not None):
+        dev = next(t.device for t in (consensus, mask, stats) if t is not None)
+    _check_outputs(n, replicas[0].dtype, dev, consensus, mask, stats)
     d = VoteDesc()
-    k = len(replicas)
-    for t in list(replicas) + [x for x in (consensus, mask) if x is not None]:
-        if not t.is_contiguous():
-            raise ValueError("replicas and outputs must be contiguous tensors")
     for r, t in enumerate(replicas):
         d.replicas[r] = t.data_ptr()
-    d.k = k
+    d.k = len(replicas)
     d.dtype = dtype_code(replicas[0])
-    d.n = int(replicas[0].numel() if n is None else n)
+    d.n = n
     d.tol = tol
     d.consensus = consensus.data_ptr() if consensus is not None else None
     d.mask = mask.data_ptr() if mask is not None else None
@@ -303,6 +373,8 @@ def make_desc(replicas, tol: Tol, consensus=None, mask=None, stats=None, n=None)
 def vote(ctx: Context, replicas, tol: Tol, consensus=None, mask=None, stats=None, stream=None,
          want_consensus: bool = True, want_mask: bool = True):
     """ftv_vote on k device tensors of one dtype; returns (consensus, mask, stats buffer)."""
+    n, dev = _check_replicas(replicas)
+    _check_outputs(n, replicas[0].dtype, dev, consensus, mask, stats)
     torch = _torch()
     x0 = replicas[0]
     if consensus is None and want_consensus:
@@ -320,8 +392,11 @@ def vote_mem(ctx: Context, replicas, tol: Tol, consensus=None, mask=None, stats=
              stream=None, want_consensus: bool = True, want_mask: bool = True):
     """ftv_vote_mem: replicas are torch tensors in host memory (CPU tensors,
     pinned or not) or on the GPU; outputs are device tensors."""
+    n, dev = _check_replicas(replicas, host_ok=True)
     torch = _torch()
-    dev = next((r.device for r in replicas if r.is_cuda), torch.device("cuda", torch.cuda.current_device()))
+    if dev is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    _check_outputs(n, replicas[0].dtype, dev, consensus, mask, stats)
     x0 = replicas[0]
     if consensus is None and want_consensus:
         consensus = torch.empty(x0.numel(), dtype=x0.dtype, device=dev)
@@ -329,7 +404,7 @@ def vote_mem(ctx: Context, replicas, tol: Tol, consensus=None, mask=None, stats=
         mask = torch.empty(x0.numel(), dtype=torch.uint8, device=dev)
     if stats is None:
         stats = stats_tensor(dev)
-    d = make_desc(replicas, tol, consensus, mask, stats)
+    d = make_desc(replicas, tol, consensus, mask, stats, host_ok=True)
     mem = (ctypes.c_int32 * len(replicas))(*[MEM_DEVICE if r.is_cuda else MEM_HOST for r in replicas])
     _check(load().ftv_vote_mem(ctx.handle, ctypes.byref(d), mem, c_uint64(int(chunk_bytes)),
                                c_void_p(_stream_handle(stream))))
@@ -350,9 +425,12 @@ def tune_batch(ctx: Context, descs, iters: int = 3, stream=None) -> BatchCfg:
 
 
 def fingerprint(ctx: Context, buf, block_bytes: int = 65536, out=None, stream=None):
-    torch = _torch()
+    _check_tensor(buf, "buffer")
     nbytes = buf.numel() * buf.element_size()
-    nblocks = (nbytes + block_bytes - 1) // block_bytes
+    nblocks = (nbytes + block_bytes - 1) // block_bytes if block_bytes > 0 else 0
+    if out is not None:
+        _check_tensor(out, "fingerprint output", device=buf.device, min_bytes=8 * nblocks)
+    torch = _torch()
     if out is None:
         out = torch.empty(nblocks, dtype=torch.int64, device=buf.device)
     _check(load().ftv_fingerprint(ctx.handle, c_void_p(buf.data_ptr()), nbytes, block_bytes,
@@ -378,12 +456,19 @@ def vote_blocks(ctx: Context, replicas, fallback_tol: Tol, block_bytes: int = 65
                 want_fps: bool = True, want_mask: bool = True, consensus=None, mask=None,
                 blockmap=None, fps=None, bstats=None, stream=None):
     """ftv_vote_blocks; returns dict of device tensors (fps, blockmap, consensus, mask, bstats)."""
-    torch = _torch()
+    n, dev = _check_replicas(replicas)
     x0 = replicas[0]
     k = len(replicas)
-    nbytes = x0.numel() * x0.element_size()
-    nblocks = (nbytes + block_bytes - 1) // block_bytes
-    dev = x0.device
+    nbytes = n * x0.element_size()
+    nblocks = (nbytes + block_bytes - 1) // block_bytes if block_bytes > 0 else 0
+    _check_outputs(n, x0.dtype, dev, consensus, mask)
+    if fps is not None:
+        _check_tensor(fps, "fps", device=dev, min_bytes=8 * k * nblocks)
+    if blockmap is not None:
+        _check_tensor(blockmap, "blockmap", device=dev, min_bytes=nblocks)
+    if bstats is not None:
+        _check_tensor(bstats, "bstats", device=dev, min_bytes=ctypes.sizeof(BlockStats))
+    torch = _torch()
     if fps is None and want_fps:
         fps = torch.empty(k * nblocks, dtype=torch.int64, device=dev)
     if blockmap is None:
@@ -417,23 +502,38 @@ class Server:
         h = c_void_p()
         _check(L.ftv_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
+        self._events = {}   # ticket -> the ready event, kept until release
 
-    def submit(self, req: Request) -> int:
+    def submit(self, req: Request, ready_event=None) -> int:
         t = c_uint64()
         _check(load().ftv_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        if ready_event is not None:
+            self._events[int(t.value)] = ready_event
         return int(t.value)
 
+    def _ready(self, req: Request, stream):
+        """Record an event after the work queued so far on `stream` (torch's
+        current stream by default), which produces the request's inputs."""
+        torch = _torch()
+        ev = torch.cuda.Event()
+        ev.record(stream if stream is not None else torch.cuda.current_stream())
+        req.ready = ev.cuda_event
+        return ev
+
     def submit_vote(self, replicas, tol: Tol, consensus=None, mask=None, t_arrival_ns: int = 0,
-                    user_tag: int = 0, n=None) -> int:
+                    user_tag: int = 0, n=None, stream=None, inputs_ready: bool = False) -> int:
+        """inputs_ready: the replicas are complete already (no event is passed)."""
         req = Request()
         req.kind = REQ_VOTE
         req.vote = make_desc(replicas, tol, consensus, mask, None, n=n)
         req.t_arrival_ns = int(t_arrival_ns)
         req.user_tag = int(user_tag)
-        return self.submit(req)
+        ev = None if inputs_ready else self._ready(req, stream)
+        return self.submit(req, ev)
 
     def submit_fingerprint(self, buf, block_bytes: int = 65536, t_arrival_ns: int = 0,
-                           user_tag: int = 0) -> int:
+                           user_tag: int = 0, stream=None, inputs_ready: bool = False) -> int:
+        _check_tensor(buf, "buffer")
         req = Request()
         req.kind = REQ_FINGERPRINT
         req.fp_buf = buf.data_ptr()
@@ -441,7 +541,8 @@ class Server:
         req.block_bytes = int(block_bytes)
         req.t_arrival_ns = int(t_arrival_ns)
         req.user_tag = int(user_tag)
-        return self.submit(req)
+        ev = None if inputs_ready else self._ready(req, stream)
+        return self.submit(req, ev)
 
     def poll(self, ticket: int, wait_us: int = -1):
         """Result structure when done, None while in flight."""
@@ -454,6 +555,7 @@ class Server:
 
     def release(self, ticket: int):
         _check(load().ftv_release(self.handle, int(ticket)))
+        self._events.pop(int(ticket), None)
 
     def stats(self) -> dict:
         st = ServerStats()
@@ -464,6 +566,7 @@ class Server:
         if self.handle:
             load().ftv_server_destroy(self.handle)
             self.handle = None
+            self._events.clear()
 
     def __del__(self):
         try:

@@ -197,3 +197,68 @@ def checkpoint_set(n: int, seed: int = SEED_BASE + 5, nstuck: int = 256, nflip: 
     flip_bits(r2, pos, bits)
     r3 = np.roll(base, 1)
     return [base, r1, r2, r3, base.copy()]
+
+
+# --------------------------------------------------------------------------
+# planted fault patterns (exact fault counts per replica, for winner cases)
+# --------------------------------------------------------------------------
+_WIDTH = {"f32": 32, "f64": 64, "i32": 32, "i64": 64}
+
+
+def _far_bit(dtype: str) -> int:
+    # an exponent bit for floats (values of U[-1,1) stay finite), a high bit for integers
+    return 30 if _WIDTH[dtype] == 32 else 62
+
+
+def _split_bit(dtype: str, r: int) -> int:
+    # replica r's own bit for elements where every replica holds another value
+    return (20 if _WIDTH[dtype] == 32 else 49) + r
+
+
+def planted_set(dtype: str, n: int, per_replica, nomaj: int = 0, seed: int = SEED_BASE + 7):
+    """k = len(per_replica) replicas of one base of n elements.  Replica r is
+    changed at per_replica[r] positions of its own (no position is shared by two
+    replicas, so all other replicas agree there), and `nomaj` further positions
+    hold a different value in every replica.  Returns (base, replicas)."""
+    k = len(per_replica)
+    base = values(dtype, INTFULL if dtype[0] == "i" else UNIFORM, seed, 0, n)
+    pos = distinct_positions(n, int(sum(per_replica)) + nomaj, seed, 1).astype(np.int64)
+    reps = [base.copy() for _ in range(k)]
+    one = _u[dtype](1)
+    off = 0
+    for r, c in enumerate(per_replica):
+        reps[r].view(_u[dtype])[pos[off:off + c]] ^= one << _u[dtype](_far_bit(dtype))
+        off += c
+    for r in range(k):
+        reps[r].view(_u[dtype])[pos[off:]] ^= one << _u[dtype](_split_bit(dtype, r))
+    return base, reps
+
+
+def planted_blocks(dtype: str, nblocks: int, block_bytes: int, per_replica, unresolved_block: bool = False,
+                   tail_elems: int = 0, seed: int = SEED_BASE + 8):
+    """k = len(per_replica) replicas of nblocks blocks (+ tail_elems elements).
+    Replica r has one changed word in per_replica[r] whole blocks of its own (no
+    block is changed in two replicas).  With unresolved_block, one further block
+    has element 5 set to a different value in every replica.  Returns (base,
+    replicas, that block's index or -1)."""
+    k = len(per_replica)
+    es = _WIDTH[dtype] // 8
+    per = block_bytes // es
+    n = nblocks * per + tail_elems
+    base = values(dtype, INTFULL if dtype[0] == "i" else UNIFORM, seed, 0, n)
+    need = int(sum(per_replica)) + int(unresolved_block)
+    blocks = distinct_positions(nblocks, need, seed, 1).astype(np.int64)
+    inblk = distinct_positions(per, need, seed, 2).astype(np.int64)
+    reps = [base.copy() for _ in range(k)]
+    one = _u[dtype](1)
+    off = 0
+    for r, c in enumerate(per_replica):
+        for j in range(off, off + c):
+            reps[r].view(_u[dtype])[blocks[j] * per + inblk[j]] ^= one << _u[dtype](_far_bit(dtype))
+        off += c
+    ub = -1
+    if unresolved_block:
+        ub = int(blocks[off])
+        for r in range(k):
+            reps[r].view(_u[dtype])[ub * per + 5] ^= one << _u[dtype](_split_bit(dtype, r))
+    return base, reps, ub

@@ -56,8 +56,8 @@ int main(void) {
          sizeof(ftv_server_cfg), sizeof(ftv_request), sizeof(ftv_result), sizeof(ftv_server_stats),
          sizeof(ftv_sibling_info), sizeof(ftv_mm_check_result), sizeof(ftv_impl),
          sizeof(ftv_redundancy_cfg), sizeof(ftv_redundancy_report));
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(ftv_stats, verdict), offsetof(ftv_vote_desc, tol),
-         offsetof(ftv_vote_desc, stats), offsetof(ftv_request, t_arrival_ns),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", offsetof(ftv_stats, verdict), offsetof(ftv_vote_desc, tol),
+         offsetof(ftv_vote_desc, stats), offsetof(ftv_request, t_arrival_ns), offsetof(ftv_request, ready),
          offsetof(ftv_sibling_info, readers), offsetof(ftv_mm_check_result, blocks),
          offsetof(ftv_redundancy_cfg, tol), offsetof(ftv_redundancy_report, seconds));
   return 0;
@@ -82,7 +82,7 @@ def test_ctypes_layout_matches_c():
                                        b.RedundancyReport)]
     assert mine == sizes
     assert [b.Stats.verdict.offset, b.VoteDesc.tol.offset, b.VoteDesc.stats.offset,
-            b.Request.t_arrival_ns.offset, b.SiblingInfo.readers.offset,
+            b.Request.t_arrival_ns.offset, b.Request.ready.offset, b.SiblingInfo.readers.offset,
             b.MMCheckResult.blocks.offset, b.RedundancyCfg.tol.offset,
             b.RedundancyReport.seconds.offset] == offs
 

@@ -173,3 +173,42 @@ def test_tune_cache_roundtrip(gpu, ctx, tmp_path, monkeypatch):
     again = gpu.tune_batch(ctx, descs, iters=1)
     assert (again.tile_vecs, again.block, again.grid_mult, again.order, again.nt_stores) == (1024, 512, 2, 2, 0)
     assert same(outputs(gpu, tasks, stats), ref)
+
+
+def test_batch_planted_nonzero_argmin_winners(gpu, ctx):
+    """Tasks whose winner is a non-zero argmin of the disagree counts
+    (ELEMENT_MAJORITY and UNRESOLVED), mixed with ordinary tasks in one batch:
+    identical to the oracle."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(515)
+    tasks, _, _ = make_batch(gpu, rng, 40, 30000, ks=(2, 3, 5))
+    cases = []
+    for dtype in ("f32", "f64", "i32", "i64"):
+        for per in ([40, 10, 30], [40, 10, 30, 10, 50], [40, 10, 30, 10, 50, 60, 70]):
+            for nomaj in (0, 2):
+                cases.append((dtype, per, nomaj))
+    for j, (dtype, per, nomaj) in enumerate(cases):
+        n = 50000 + 1237 * j
+        _, reps = synth.planted_set(dtype, n, per, nomaj, seed=synth.SEED_BASE + 100 + j)
+        if dtype[0] == "i":
+            tol_o, tol_f = oracle.exact(), gpu.exact()
+        else:
+            tol_o, tol_f = oracle.ulp(4), gpu.ulp(4)
+        t_reps = [torch.from_numpy(r).to(dev) for r in reps]
+        tasks.append(dict(reps=reps, t_reps=t_reps, tol_o=tol_o, tol_f=tol_f,
+                          cons=torch.empty(n, dtype=t_reps[0].dtype, device=dev),
+                          mask=torch.empty(n, dtype=torch.uint8, device=dev), n=n, k=len(per)))
+    stats = gpu.stats_tensor(dev, len(tasks))
+    descs = []
+    for i, t in enumerate(tasks):
+        d = gpu.make_desc(t["t_reps"], t["tol_f"], t["cons"], t["mask"], None, n=t["n"])
+        d.stats = stats.data_ptr() + i * ctypes.sizeof(gpu.Stats)
+        descs.append(d)
+    print(f"case: batch of {len(tasks)} tasks with {len(cases)} planted non-zero winners", flush=True)
+    gpu.vote_batch(ctx, descs)
+    got = outputs(gpu, tasks, stats)
+    check_oracle(tasks, got)
+    nz = sum(1 for (_, _, s) in got[-len(cases):] if s["winner"] != 0 and s["verdict"] >= 2)
+    assert nz == len(cases)

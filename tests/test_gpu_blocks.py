@@ -171,3 +171,19 @@ def test_checkpoint_full_size(gpu):
         assert blockmap[blk] == ref.blockmap[0], blk
         assert np.array_equal(cons[sl].cpu().numpy().view(np.uint64), ref.consensus.view(np.uint64)), blk
         assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), blk
+
+
+@pytest.mark.parametrize("dtype,bb", [("f64", 65536), ("f32", 4096), ("i32", 16384), ("i64", 8192)])
+def test_block_vote_planted_nonzero_argmin_winner(gpu, dtype, bb):
+    """Replica blocks with their minimum at replica 1 and every replica
+    differing somewhere: ELEMENT_MAJORITY, and UNRESOLVED with a fallback block
+    holding an element without majority -- winner a non-zero argmin, identical
+    to the oracle (a ragged tail block included)."""
+    for per in ([3, 1, 2], [3, 1, 2, 1, 4], [3, 1, 2, 1, 4, 5, 6]):
+        for unresolved in (False, True):
+            _, reps, ub = synth.planted_blocks(dtype, 40, bb, per, unresolved, tail_elems=37)
+            tol_o, tol_f = (oracle.exact(), gpu.exact()) if dtype[0] == "i" else (oracle.ulp(2), gpu.ulp(2))
+            print(f"case: planted block winner {dtype} block={bb} k={len(per)} unresolved={unresolved}", flush=True)
+            ref = _block_case(gpu, reps, tol_o, tol_f, bb)
+            assert ref.winner != 0
+            assert ref.verdict == (oracle.UNRESOLVED if unresolved else oracle.ELEMENT_MAJORITY)

@@ -248,3 +248,53 @@ def test_large_task_full_size(gpu, ctx, dtype, side, tol):
     ref = oracle.vote(reps, oracle.ulp(tol))
     _check((cons.cpu().numpy(), mask.cpu().numpy(), s), ref, 3, f"large_task_set full {dtype}")
     assert s["verdict"] == gpu.TASK_MAJORITY and s["winner"] == 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "i32", "i64"])
+def test_planted_nonzero_argmin_winner(gpu, ctx, dtype):
+    """Every replica faulty somewhere (no TASK_MAJORITY), disagree counts with
+    their minimum at replica 1 (tied with 3 for k >= 4): the winner of
+    ELEMENT_MAJORITY and of UNRESOLVED (nomaj > 0) is a non-zero argmin.  n is
+    ragged and spans many tiles of every launch shape."""
+    n = 200003
+    for per in ([40, 10, 30], [40, 10, 30, 10, 50], [40, 10, 30, 10, 50, 60, 70]):
+        for nomaj in (0, 3):
+            print(f"case: planted winner {dtype} k={len(per)} nomaj={nomaj}", flush=True)
+            _, reps = synth.planted_set(dtype, n, per, nomaj)
+            pairs = _tols(gpu, np.dtype(synth._np[dtype]))
+            tol_o, tol_f = pairs[0] if dtype[0] == "i" else pairs[2]
+            ref = oracle.vote(reps, tol_o)
+            assert ref.winner != 0
+            assert ref.verdict == (oracle.UNRESOLVED if nomaj else oracle.ELEMENT_MAJORITY)
+            _check(_run(gpu, ctx, reps, tol_f), ref, len(per), f"planted {dtype} {per} {nomaj}")
+
+
+def test_two_streams_share_a_context(gpu, ctx):
+    """Votes issued alternately on two streams with one context, never
+    synchronised in between: each stream counts in its own accumulators, so
+    every stats record equals the oracle's (never counts of the other stream)."""
+    import torch
+    dev = torch.device("cuda:0")
+    sets = []
+    for j in range(2):
+        _, reps = synth.planted_set("f32", 300001 + 17 * j, [40 + 7 * j, 10, 30 + j], 2 * j,
+                                    seed=synth.SEED_BASE + 300 + j)
+        sets.append((reps, oracle.vote(reps, oracle.ulp(4))))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    t_reps = [[torch.from_numpy(r).to(dev) for r in reps] for reps, _ in sets]
+    torch.cuda.synchronize()
+    outs = [[gpu.stats_tensor(dev) for _ in range(8)] for _ in range(2)]
+    print("case: two streams, one context, 8 interleaved votes each", flush=True)
+    for i in range(8):
+        for j in range(2):
+            with torch.cuda.stream(streams[j]):
+                gpu.vote(ctx, t_reps[j], gpu.ulp(4), stats=outs[j][i], want_consensus=False,
+                         want_mask=False, stream=streams[j])
+    torch.cuda.synchronize()
+    for j in range(2):
+        ref = sets[j][1]
+        for i in range(8):
+            s = gpu.read_stats(outs[j][i])
+            assert np.array_equal(s["pair"][:3, :3], ref.pair), (j, i)
+            assert np.array_equal(s["disagree"][:3], ref.disagree), (j, i)
+            assert s["no_majority"] == ref.no_majority and (s["verdict"], s["winner"]) == (ref.verdict, ref.winner)

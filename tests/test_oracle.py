@@ -333,6 +333,75 @@ def test_verdict_ladder():
     assert res.verdict == oracle.TASK_MAJORITY and res.winner == 0
 
 
+def _plant_k5(per_replica, no_majority_element=False, n=64):
+    """k = 5 fp32 replicas of arange(n) with replica r wrong (value 1000 + r) on
+    per_replica[r] elements of its own, no element shared by two replicas, so
+    that every element keeps a 4-of-5 majority.  With no_majority_element,
+    element n-1 holds a, a, b, b, c (support 2, 2, 2, 2, 1): no strict majority,
+    candidates {a, a, b, b}, lower median a = replicas 0 and 1, so replicas
+    2, 3 and 4 are flagged there."""
+    x = np.arange(n, dtype=np.float32)
+    reps = [x.copy() for _ in range(5)]
+    pos = 0
+    for r, cnt in enumerate(per_replica):
+        for _ in range(cnt):
+            reps[r][pos] = 1000.0 + r
+            pos += 1
+    assert pos < n - 1
+    if no_majority_element:
+        for r, v in enumerate((-5.0, -5.0, 7.0, 7.0, 9.0)):
+            reps[r][n - 1] = v
+    return x, reps
+
+
+def test_winner_is_argmin_of_disagree_element_majority():
+    """Sec. IV-D winner rule outside TASK_MAJORITY: the replica with the fewest
+    disagreements, the lowest index on ties.  Disagree counts (3,1,2,1,4) make
+    argmin-lowest = 1, argmin-highest = 3, argmax = 4, and replica 0 (the
+    default) a loser; every replica has a fault of its own, so no replica
+    agrees with another over the whole task (support 1 each: no TASK_MAJORITY)."""
+    x, reps = _plant_k5((3, 1, 2, 1, 4))
+    res = oracle.vote(reps, oracle.ulp(4))
+    assert list(res.disagree) == [3, 1, 2, 1, 4]
+    assert res.no_majority == 0 and np.array_equal(res.consensus, x)
+    assert res.verdict == oracle.ELEMENT_MAJORITY
+    assert res.winner == 1
+
+
+def test_winner_is_argmin_of_disagree_unresolved():
+    """The same counts reached with one element that has no majority: planted
+    faults (3,1,1,0,3) plus the a,a,b,b,c element adding one to replicas 2, 3, 4."""
+    x, reps = _plant_k5((3, 1, 1, 0, 3), no_majority_element=True)
+    res = oracle.vote(reps, oracle.ulp(4))
+    assert list(res.disagree) == [3, 1, 2, 1, 4]
+    assert res.no_majority == 1 and res.mask[-1] == 0x80 | 0b11100
+    assert res.consensus[-1] == np.float32(-5.0)
+    assert res.verdict == oracle.UNRESOLVED
+    assert res.winner == 1
+
+
+def test_task_majority_needs_a_strict_majority_of_replicas():
+    """k = 4: replicas 0 and 1 agree everywhere, 2 and 3 each have faults of
+    their own.  Task support T = (2, 2, 1, 1) and 2*2 > 4 is false: no replica
+    is a valid result alone, the consensus is (ELEMENT_MAJORITY, winner = the
+    lowest replica with no disagreement)."""
+    x = np.arange(16, dtype=np.float32)
+    reps = [x.copy(), x.copy(), x.copy(), x.copy()]
+    reps[2][3] = 100.0
+    reps[3][5] = 200.0
+    reps[3][6] = 300.0
+    res = oracle.vote(reps, oracle.ulp(4))
+    assert list(res.disagree) == [0, 0, 1, 2]
+    assert res.verdict == oracle.ELEMENT_MAJORITY and res.winner == 0
+    # k = 5 with three replicas clean: T = 3 for them, 2*3 > 5 -> TASK_MAJORITY,
+    # lowest such replica; replica 0 is faulty so the winner is 1
+    reps = [x.copy() for _ in range(5)]
+    reps[0][1] = 50.0
+    reps[3][2] = 60.0
+    res = oracle.vote(reps, oracle.ulp(4))
+    assert res.verdict == oracle.TASK_MAJORITY and res.winner == 1
+
+
 def test_fp64_and_int64_paths():
     rng = np.random.default_rng(10)
     a = rng.standard_normal(500)
@@ -472,3 +541,95 @@ def test_block_vote_no_majority_falls_back_to_element_vote():
     assert res.mask[3 * 512 + 10] & 2 and res.mask[3 * 512 + 400] & 4
     assert res.mask[3 * 512 + 11] == 8   # the rotated replica, flagged element-wise
     assert not res.mask[:3 * 512].any()
+
+
+def _block_reps_k5(n_blocks, per=512):
+    """k = 5 fp64 replicas of distinct random words, n_blocks blocks of 4 KiB."""
+    base = synth.values("f64", synth.NORMAL, 21, 0, n_blocks * per)
+    return base, [base.copy() for _ in range(5)]
+
+
+def _corrupt_blocks(reps, plan, per=512):
+    """plan: list of (replica, block): one word of that block changed in that
+    replica; each block is corrupted in at most one replica, so every block keeps
+    a 4-of-5 fingerprint majority."""
+    for r, b in plan:
+        reps[r].view(np.uint64)[b * per + 7] ^= np.uint64(1 << 33)
+
+
+def test_block_vote_winner_is_argmin_element_majority():
+    """Replica blocks (3,1,2,1,4): every replica differs somewhere, no fallback
+    block -> ELEMENT_MAJORITY with winner = the lowest index of the fewest
+    differing blocks (1; argmax would give 4, highest-index ties 3)."""
+    base, reps = _block_reps_k5(16)
+    plan = [(0, 0), (0, 1), (0, 2), (1, 3), (2, 4), (2, 5), (3, 6), (4, 7), (4, 8), (4, 9), (4, 10)]
+    _corrupt_blocks(reps, plan)
+    res = oracle.vote_blocks(reps, oracle.exact(), 4096)
+    assert list(res.replica_blocks) == [3, 1, 2, 1, 4]
+    assert res.fallback_blocks == 0 and res.disagree_blocks == 11
+    assert np.array_equal(res.consensus.view(np.uint64), base.view(np.uint64))
+    for r, b in plan:
+        assert res.blockmap[b] == 1 << r
+    assert res.verdict == oracle.ELEMENT_MAJORITY and res.winner == 1
+
+
+def test_block_vote_unresolved_and_its_winner():
+    """One block with fingerprints a,a,b,b,c (support 2,2,2,2,1: no strict
+    majority) falls back to the element vote, whose element 9 also has no
+    majority (replicas 2 and 3 agree on another value, replica 4 on a third):
+    UNRESOLVED.  The source of that block is replica 0 (the lowest of maximal
+    support), so replicas 2, 3, 4 are counted as differing there; with the
+    majority-block faults (3,1,1,0,3) the replica blocks are (3,1,2,1,4) and the
+    winner is replica 1."""
+    per = 512
+    base, reps = _block_reps_k5(16)
+    plan = [(0, 0), (0, 1), (0, 2), (1, 3), (2, 4), (4, 7), (4, 8), (4, 10)]
+    _corrupt_blocks(reps, plan)
+    fb = 12
+    w = [r.view(np.uint64) for r in reps]
+    w[2][fb * per + 9] = w[3][fb * per + 9] = np.uint64(0x3FF0000000000000)   # 1.0
+    w[4][fb * per + 9] = np.uint64(0x4000000000000000)                        # 2.0
+    res = oracle.vote_blocks(reps, oracle.exact(), 4096)
+    assert res.blockmap[fb] == 0x80 | 0b11100
+    assert res.fallback_blocks == 1 and res.unresolved_elems == 1
+    assert list(res.replica_blocks) == [3, 1, 2, 1, 4]
+    assert res.mask[fb * per + 9] == 0x80 | 0b11100
+    # element 9 has candidates {base, base, 1.0, 1.0}; the lower median under
+    # totalOrder is the smaller of base[9] and 1.0
+    lo = min(float(base[fb * per + 9]), 1.0)
+    assert res.consensus[fb * per + 9] == lo
+    assert res.verdict == oracle.UNRESOLVED and res.winner == 1
+
+
+def test_block_vote_task_majority_winner_is_lowest_clean_replica():
+    """Replica 0 differs in one block and replica 1 nowhere: TASK_MAJORITY with
+    winner 1 (not the default 0), and the consensus is restored from replica 1
+    in the block where replica 0 is the outlier."""
+    base, reps = _block_reps_k5(8)
+    _corrupt_blocks(reps, [(0, 2), (2, 5)])
+    res = oracle.vote_blocks(reps, oracle.exact(), 4096)
+    assert res.verdict == oracle.TASK_MAJORITY and res.winner == 1
+    assert np.array_equal(res.consensus.view(np.uint64), base.view(np.uint64))
+
+
+def test_threaded_vote_is_the_sequential_vote():
+    """The host-core timing leg (the element loop split over OpenMP threads,
+    counters summed per thread) gives the sequential oracle's bits and counts,
+    for every thread count, on a set with every kind of fault and ragged
+    per-thread ranges."""
+    cases = [(synth.small_task_set(n=100003), oracle.ulp(4)),
+             (synth.planted_set("f64", 77777, [40, 10, 30, 10, 50], 3)[1], oracle.ulp(2)),
+             (synth.planted_set("i32", 5001, [5, 1, 3], 1)[1], oracle.exact()),
+             (synth.large_task_set(65536, "f32", flip_rate=1e-4), oracle.rel(1e-3))]
+    for reps, tol in cases:
+        ref = oracle.vote(reps, tol)
+        u = np.uint32 if reps[0].itemsize == 4 else np.uint64
+        for nt in (1, 2, 3, 7, 16):
+            got, used = oracle.vote_threads(reps, tol, nt)
+            assert used == nt
+            assert np.array_equal(got.consensus.view(u), ref.consensus.view(u))
+            assert np.array_equal(got.mask, ref.mask)
+            assert np.array_equal(got.pair, ref.pair) and np.array_equal(got.disagree, ref.disagree)
+            assert (got.no_majority, got.verdict, got.winner) == (ref.no_majority, ref.verdict, ref.winner)
+    got, used = oracle.vote_threads([np.zeros(0, np.float32)] * 3, oracle.ulp(4), 4)
+    assert got.verdict == oracle.UNANIMOUS and got.mask.size == 0
