@@ -196,6 +196,26 @@ int ftv_vote_mem(ftv_ctx *ctx, const ftv_vote_desc *desc, const int32_t *memory,
  * than 2^32 - 1 tasks or tiles), FTV_E_NOMEM (table growth), FTV_E_HIP. */
 int ftv_vote_batch(ftv_ctx *ctx, const ftv_vote_desc *descs, uint64_t ntasks, void *stream);
 
+/* ftv_vote_batch_noalloc -- for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * batched vote of ftv_vote_batch (same descriptors, same rules, identical
+ * results) with no context and no allocation of any kind: the task table, tile
+ * queue and count accumulators live in a static device array of the library,
+ * FTV_NOALLOC_SCRATCH_BYTES on every GPU it runs on, held until the process
+ * ends.  Work goes to the CURRENT device on `stream`, with ftv_vote_batch's
+ * default schedule (kernels launched directly, no graph).  The host side
+ * builds the table in static host arrays under one lock and uploads it from
+ * pageable memory (a blocking copy for the host).  Every call on a GPU shares
+ * that GPU's array and clears what it needs first; calls on one stream are
+ * ordered by it, but calls whose work overlaps on one GPU (other streams,
+ * other threads, without an event between them) race and give wrong results:
+ * order them.  Errors: those of ftv_vote_batch, and FTV_E_INVALID for more
+ * than FTV_NOALLOC_MAX_TASKS tasks (nothing is enqueued) or a device index
+ * above 63. */
+#define FTV_NOALLOC_MAX_TASKS 4096
+#define FTV_NOALLOC_SCRATCH_BYTES (1792u * 1024u)
+int ftv_vote_batch_noalloc(const ftv_vote_desc *descs, uint64_t ntasks, void *stream);
+
 /* Schedule of the batched launch, chosen by ftv_tune_batch.  None of these
  * fields can change a result, only the time taken. */
 typedef struct ftv_batch_cfg {

@@ -25,6 +25,7 @@ TOL_EXACT, TOL_ULP, TOL_REL = 0, 1, 2
 UNANIMOUS, TASK_MAJORITY, ELEMENT_MAJORITY, UNRESOLVED = 0, 1, 2, 3
 MAX_K = 7
 MASK_NOMAJ = 0x80
+NOALLOC_MAX_TASKS = 4096
 REQ_VOTE, REQ_FINGERPRINT = 0, 1
 
 
@@ -129,7 +130,7 @@ EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv
            "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote",
            "ftv_mm_create", "ftv_mm_destroy", "ftv_mm_register", "ftv_mm_request", "ftv_mm_release",
            "ftv_mm_siblings", "ftv_mm_check", "ftv_run_redundant", "ftv_vote_mem",
-           "ftv_ctx_set_timing", "ftv_ctx_kernel_times"]
+           "ftv_ctx_set_timing", "ftv_ctx_kernel_times", "ftv_vote_batch_noalloc"]
 
 _lib = None
 
@@ -160,6 +161,7 @@ def load():
     L.ftv_ctx_set_timing.argtypes = [vp, c_int]
     L.ftv_ctx_kernel_times.argtypes = [vp, POINTER(ctypes.c_float), c_uint32, POINTER(c_uint32)]
     L.ftv_vote_batch.argtypes = [vp, POINTER(VoteDesc), c_uint64, vp]
+    L.ftv_vote_batch_noalloc.argtypes = [POINTER(VoteDesc), c_uint64, vp]
     L.ftv_vote_mem.argtypes = [vp, POINTER(VoteDesc), POINTER(ctypes.c_int32), c_uint64, vp]
     L.ftv_batch_get_config.argtypes = [vp, POINTER(BatchCfg)]
     L.ftv_batch_set_config.argtypes = [vp, POINTER(BatchCfg)]
@@ -414,6 +416,13 @@ def vote_mem(ctx: Context, replicas, tol: Tol, consensus=None, mask=None, stats=
 def vote_batch(ctx: Context, descs, stream=None):
     arr = (VoteDesc * len(descs))(*descs)
     _check(load().ftv_vote_batch(ctx.handle, arr, len(descs), c_void_p(_stream_handle(stream))))
+
+
+def vote_batch_noalloc(descs, stream=None):
+    """ftv_vote_batch_noalloc: the batched vote without a context or any
+    allocation (at most NOALLOC_MAX_TASKS descriptors), on the current device."""
+    arr = (VoteDesc * max(len(descs), 1))(*descs)
+    _check(load().ftv_vote_batch_noalloc(arr, len(descs), c_void_p(_stream_handle(stream))))
 
 
 def tune_batch(ctx: Context, descs, iters: int = 3, stream=None) -> BatchCfg:
