@@ -570,6 +570,67 @@ def bench_mixed(ftv, ctx, side=16384, reps_timed=3, chunk_mib=64):
     return out
 
 
+def bench_placement(ftv, ctx, runs=5):
+    """Voter units by data size (the paper's Fig. 3 analogue): k=3 fp32 replicas
+    of 1 KiB .. 64 MiB each, in host memory and in device memory, voted by one
+    host thread, all host cores and the MI355X voter (each forced through
+    ftv_vote_placed by avoiding the other two); the median wall time of each
+    unit's whole run, transfers included.  Then the placement itself, left to
+    learn: the unit it settles on per size."""
+    import torch
+    import synth
+    log("bench: voter placement by size (host / device data, three units)")
+    units = [ftv.VOTER_HOST1, ftv.VOTER_HOSTMT, ftv.VOTER_GPU]
+    names = {ftv.VOTER_HOST1: "host_1_thread", ftv.VOTER_HOSTMT: "host_all_cores", ftv.VOTER_GPU: "gpu"}
+    sizes = [1 << s for s in range(10, 27, 2)]            # bytes per replica
+    full = synth.small_task_set(n=max(sizes) // 4)
+    tol = ftv.ulp(4)
+    rows = []
+    for where in ("host", "device"):
+        for nbytes in sizes:
+            n = nbytes // 4
+            reps = [torch.from_numpy(r[:n].copy()) for r in full]
+            if where == "device":
+                reps = [r.cuda() for r in reps]
+            torch.cuda.synchronize()
+            row = {"data": where, "bytes_per_replica": nbytes}
+            results = []
+            for u in units:
+                db = ftv.VoterDB(check_interval=0, host_threads=0)
+                avoid = sum(1 << v for v in units if v != u)
+                ts = []
+                for _ in range(runs + 1):
+                    cons, mask, st, rep = ftv.vote_placed(ctx, db, reps, tol, out_memory=ftv.MEM_DEVICE
+                                                          if where == "device" else ftv.MEM_HOST, avoid=avoid)
+                    ts.append(rep["seconds"][0])
+                db.close()
+                ts = sorted(ts[1:])
+                row[names[u] + "_us"] = round(ts[len(ts) // 2] * 1e6, 1)
+                results.append((cons.cpu() if cons.is_cuda else cons).numpy().view("u4").copy())
+            row["identical"] = all((x == results[0]).all() for x in results[1:])
+            row["fastest"] = min((row[names[u] + "_us"], names[u]) for u in units)[1]
+            # the placement left to itself: what it settles on after trying every unit
+            db = ftv.VoterDB(check_interval=0, host_threads=0)
+            chosen = []
+            for _ in range(8):
+                chosen.append(ftv.vote_placed(ctx, db, reps, tol, out_memory=ftv.MEM_DEVICE
+                                              if where == "device" else ftv.MEM_HOST)[3]["result_unit"])
+            db.close()
+            row["placed_after_learning"] = names[chosen[-1]]
+            rows.append(row)
+            del reps
+    cross = {}
+    for where in ("host", "device"):
+        rs = [r for r in rows if r["data"] == where]
+        gpu_from = next((r["bytes_per_replica"] for r in rs if r["fastest"] == "gpu"), None)
+        mt_from = next((r["bytes_per_replica"] for r in rs if r["fastest"] == "host_all_cores"), None)
+        cross[where] = {"all_cores_fastest_from_bytes": mt_from, "gpu_fastest_from_bytes": gpu_from}
+    torch.cuda.empty_cache()
+    return {"workload": "k=3 fp32 replicas (the parity recipe) of 1 KiB .. 64 MiB each, ULP 4; per unit the "
+                        "median of %d runs, transfers of replicas and outputs included" % runs,
+            "rows": rows, "crossover": cross}
+
+
 def bench_redundant(ftv, ctx, side=16384, calls=7):
     """Three implementations of the 1 GiB fp32 task (stand-ins: each copies one
     of the large task's replicas into its output), DMR on the two with the
@@ -736,7 +797,7 @@ def main():
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
-    ap.add_argument("--only", choices=["batched", "blocks", "mixed", "ramp"],
+    ap.add_argument("--only", choices=["batched", "blocks", "mixed", "ramp", "placement"],
                     help="run only this workload and print its result (for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -759,7 +820,8 @@ def main():
         run = {"batched": lambda: bench_batched(ftv, ctx, args.batch_tasks),
                "blocks": lambda: bench_blocks(ftv, ctx),
                "mixed": lambda: bench_mixed(ftv, ctx),
-               "ramp": lambda: bench_serving_ramp(ftv, ctx)}[args.only]
+               "ramp": lambda: bench_serving_ramp(ftv, ctx),
+               "placement": lambda: bench_placement(ftv, ctx)}[args.only]
         res = run()
         ctx.close()
         print(json.dumps({args.only: res}), flush=True)
@@ -807,6 +869,7 @@ def main():
         out["blocks"] = bench_blocks(ftv, ctx)
         out["siblings"] = bench_siblings(ftv)
         out["redundant"] = bench_redundant(ftv, ctx)
+        out["placement"] = bench_placement(ftv, ctx)
         out["mixed_memory"] = bench_mixed(ftv, ctx)
         out["serving"] = bench_serving(ftv, ctx, args.serve_seconds, n_span=4, n_rand=12)
         out["serving_ramp"] = bench_serving_ramp(ftv, ctx, min(2.0, args.serve_seconds))

@@ -8,7 +8,7 @@
  * result.  Values of integer type are compared bit-wise; floating-point values
  * are equal when they differ by no more than a programmer-set maximum, because
  * diverse kernels on diverse processing units order and round differently
- * (Sec. IV-D; the paper uses a delta of 0.1% for single precision).  The type a
+ * (Sec. IV-D; the paper's experiments allow 0.1% in single precision).  The type a
  * buffer is registered with selects its compare method (Sec. IV-E).  The voter
  * is itself an ordinary task that can run on any device (Sec. IV-D), here one
  * MI355X.
@@ -51,6 +51,8 @@ extern "C" {
 #define FTV_E_BUSY (-7)     /* server queue full; context stream slots exhausted */
 #define FTV_E_NOTREADY (-8) /* ftv_poll: request still in flight */
 #define FTV_E_CLOSED (-9)   /* server shutting down / unknown ticket */
+#define FTV_E_MISMATCH (-10) /* redundant voters disagree with no majority among them;
+                                no voter unit left for a placed vote */
 
 /* ---- value types (Sec. IV-E: registration carries the value type) --------- */
 #define FTV_F32 0
@@ -184,6 +186,18 @@ int ftv_ctx_kernel_times(ftv_ctx *ctx, float *ms, uint32_t cap, uint32_t *count)
 int ftv_vote_mem(ftv_ctx *ctx, const ftv_vote_desc *desc, const int32_t *memory, uint64_t chunk_bytes,
                  void *stream);
 
+/* ftv_vote_host -- the same vote on the host's cores.  The paper keeps the
+ * voter as kernels for several processing units -- single-threaded, OpenMP
+ * and GPU -- because which one is fastest depends on the data size (Sec. V-A,
+ * Fig. 3).  Every pointer in `desc` is HOST memory (replicas, consensus,
+ * mask, stats).  threads = 1: the calling thread only; 0: one thread per core
+ * the process may use; otherwise that many threads (OpenMP).  Results are
+ * bit-identical to ftv_vote on the same replicas.  Synchronous: outputs are
+ * complete when the call returns.  Needs no GPU.  Errors: FTV_E_INVALID,
+ * FTV_E_DTYPE, FTV_E_K, FTV_E_ALIGN (a pointer not a multiple of the element
+ * size; stats not 8-byte aligned). */
+int ftv_vote_host(const ftv_vote_desc *desc, uint32_t threads);
+
 /* ftv_vote_batch -- ntasks independent votes (any mix of value types, k and
  * tolerances) in ONE persistent kernel launch, replayed from a captured HIP
  * graph (the small-task motivation: Sec. V-A, the voter's best device depends
@@ -285,14 +299,17 @@ typedef struct ftv_block_stats {
  * ftv_vote under `fallback_tol` over that block's elements.
  * replicas: HOST array of k device pointers, each 16-byte aligned.
  * nbytes: a multiple of the element size.  block_bytes: power of two in
- * [4096, 65536].  fps: k * nblocks uint64 (replica-major) or NULL.
+ * [4096, 65536].  fps: k * nblocks uint64 (replica-major) or NULL (the
+ * context then keeps them in a workspace of its own, grown on demand; such
+ * calls on different streams are ordered one after the other).
  * blockmap: nblocks bytes: bit r = replica r's fingerprint differs from the
  * source's, bit 7 = no fingerprint majority.  consensus: nbytes, 16-byte
  * aligned.  mask: n bytes (4-byte aligned) or NULL; 0 outside fallback blocks,
  * element-vote mask inside them.  bstats: device, 8-byte aligned.
  * Errors: FTV_E_INVALID (NULL argument, block size, nbytes not a multiple of
  * the element size, more than 2^31 - 1 blocks), FTV_E_K, FTV_E_DTYPE (also an
- * illegal fallback tolerance), FTV_E_ALIGN, FTV_E_HIP. */
+ * illegal fallback tolerance), FTV_E_ALIGN, FTV_E_NOMEM (fingerprint
+ * workspace), FTV_E_HIP. */
 int ftv_vote_blocks(ftv_ctx *ctx, const void *const *replicas, uint32_t k, int32_t dtype,
                     uint64_t nbytes, uint64_t block_bytes, const ftv_tol *fallback_tol,
                     uint64_t *fps, uint8_t *blockmap, void *consensus, uint8_t *mask,
@@ -401,6 +418,9 @@ typedef struct ftv_unit {
   double runtime;   /* R_i: fault-free runtime (any unit, > 0) */
   uint64_t valid;   /* v_i */
   uint64_t total;   /* t_i (0 = no history: F_i = R_i) */
+  uint64_t skipped; /* decisions that passed the unit over while F_i was
+                       +infinity, since it last ran (the check interval's
+                       counter; see ftv_run_redundant and the voter database) */
 } ftv_unit;
 
 /* F_i of one unit; +infinity when valid == 0 < total; NaN for bad input
@@ -526,10 +546,17 @@ int ftv_mm_check(ftv_mm *mm, uint32_t area, uint64_t block_bytes, void *stream,
  * everywhere, and the runtime of a valid run's unit becomes the running mean
  * of its valid runs' GPU times.  An UNRESOLVED vote changes no profile and
  * starts the next attempt, re-ranked; fewer than two implementations left
- * end the call.  Readings: the paper restarts with "the next best
+ * end the call.  Check intervals (Sec. IV-B: a unit with p = 1 is only used
+ * in predefined check intervals): when cfg->check_interval > 0, each attempt
+ * passes over the units with F = +infinity that are not among its k runs,
+ * adding 1 to their `skipped`; the first (in rank order) whose count would
+ * reach check_interval instead runs as an extra replica of the attempt
+ * (k + 1 runs, at most FTV_MAX_K) and is voted and counted like the others,
+ * so a unit that has recovered regains a finite F; a unit that runs has its
+ * count reset to 0.  Readings: the paper restarts with "the next best
  * combination" after a fault and votes DMR pairs; the exclusion rule, the
- * running mean and counting a failed run as an invalid one are this
- * library's. */
+ * running mean, counting a failed run as an invalid one and re-trying as an
+ * extra replica are this library's. */
 typedef int (*ftv_task_fn)(void *user, void *out, void *stream);
 
 typedef struct ftv_impl {
@@ -546,7 +573,8 @@ typedef struct ftv_redundancy_cfg {
   uint32_t max_attempts;   /* >= 1 */
   double timeout_factor;   /* deadline = profiled runtime x factor; 0 = none */
   int32_t dtype;           /* FTV_F32 .. FTV_I64 */
-  uint32_t reserved;       /* 0 */
+  uint32_t check_interval; /* re-try a unit with F = +infinity every this many
+                              attempts that pass it over (0 = never) */
   ftv_tol tol;             /* the vote's tolerance */
 } ftv_redundancy_cfg;
 
@@ -570,6 +598,74 @@ typedef struct ftv_redundancy_report {
  * thread-safe per context. */
 int ftv_run_redundant(ftv_ctx *ctx, const ftv_impl *impls, uint32_t nimpl, ftv_unit *units, uint32_t nunits,
                       const ftv_redundancy_cfg *cfg, uint64_t n, void *out, ftv_redundancy_report *rep);
+
+/* ---- placement of the voter (Sec. IV-B, IV-D, V-A) -------------------------
+ * The voter is a task like any other: the runtime keeps past runtimes per
+ * problem size and past fault rates for each of its kernels and runs the one
+ * with the lowest fault-aware runtime F = R / (1 - p) (see ftv_unit below);
+ * the voter may itself be run redundantly, preferably on another device than
+ * the one that computed the results.  Voter units: */
+#define FTV_VOTER_HOST1 0  /* ftv_vote_host on one thread */
+#define FTV_VOTER_HOSTMT 1 /* ftv_vote_host on the database's host threads */
+#define FTV_VOTER_GPU 2    /* the MI355X voter (ftv_vote_mem: host replicas streamed in) */
+#define FTV_NUM_VOTERS 3
+#define FTV_PLACE_REDUNDANT 1u /* run a second voter and require identical results */
+
+/* Performance database of the voter units: one profile (ftv_unit: runtime of
+ * valid runs in seconds, valid runs, runs) per unit, size class (floor of
+ * log2 of k * n * element size) and data placement (which replicas lie in
+ * host memory, where the outputs go), plus pinned host and device staging for
+ * the transfers.  check_interval: a unit whose runs for a key have all failed
+ * (F = +infinity) is re-tried, as an extra run checked against the returned
+ * result, after it has been passed over check_interval - 1 times for that key
+ * (0 = never re-tried).  host_threads: threads of FTV_VOTER_HOSTMT (0 = all
+ * cores).  Calls on one database are serialised.  Errors: FTV_E_INVALID,
+ * FTV_E_NOMEM. */
+typedef struct ftv_voter_db ftv_voter_db;
+int ftv_voter_db_create(uint32_t check_interval, uint32_t host_threads, ftv_voter_db **out);
+int ftv_voter_db_destroy(ftv_voter_db *db);
+/* The profile of `unit` for a task of `bytes` replica bytes (k * n * element
+ * size) with replicas r in host memory where bit r of host_mask is set and
+ * outputs in out_memory; all zero if the unit never ran for that key. */
+int ftv_voter_db_profile(ftv_voter_db *db, uint32_t unit, uint64_t bytes, uint32_t host_mask,
+                         int32_t out_memory, ftv_unit *out);
+/* Fault injection for tests of the fault handling: the next `count` runs of
+ * `unit` return a corrupted result (one bit of consensus element 0 flipped, or
+ * no_majority + 1 when there is no consensus output).  count = 0 clears it. */
+int ftv_voter_db_inject(ftv_voter_db *db, uint32_t unit, uint32_t count);
+
+typedef struct ftv_place_report {
+  int32_t unit[3];        /* units that ran, in order; -1 = no run */
+  uint32_t runs;          /* number of runs */
+  int32_t result_unit;    /* unit whose result is in the caller's outputs */
+  int32_t agreed;         /* FTV_PLACE_REDUNDANT: 1 if the first two voters agreed */
+  uint32_t probed;        /* 1 if a unit with F = +infinity was re-tried */
+  uint32_t reserved;
+  double seconds[3];      /* wall time of each run, transfers included */
+} ftv_place_report;
+
+/* ftv_vote_placed -- one vote, run by the voter unit of lowest F for its size
+ * class and data placement.  memory[r] (HOST array of k) says where
+ * replicas[r] lies (FTV_MEM_HOST / FTV_MEM_DEVICE); consensus, mask and stats
+ * lie in out_memory.  A unit's time is the wall time of its whole run: copies
+ * of device replicas to the host for the host units, streaming of host
+ * replicas for the GPU unit (ftv_vote_mem, 64 MiB pieces), and the copies of
+ * the outputs to out_memory.  Every unit runs once per key before F decides
+ * (a unit never run has no F).  Units in the bit set `avoid` (1 << unit) are
+ * used only when no other is left -- e.g. the unit that computed the results.
+ * A unit whose run fails directly (an error code) counts as a run that was
+ * not valid and the next unit runs.  With FTV_PLACE_REDUNDANT a second unit,
+ * on the other device than the first if possible, votes into the database's
+ * staging and both results (consensus, mask and stats) must be identical;
+ * if not, a third unit votes and the result two of them share is returned
+ * (the odd unit's run counts as not valid); three different results return
+ * FTV_E_MISMATCH.  Without the flag a run is valid unless it fails directly.
+ * Synchronous: `stream` (a hipStream_t) carries the GPU work and the copies
+ * and is synchronised before the call returns.  Errors: those of ftv_vote,
+ * FTV_E_INVALID (memory flags, out_memory, flags, avoid), FTV_E_MISMATCH,
+ * FTV_E_NOMEM, FTV_E_HIP. */
+int ftv_vote_placed(ftv_ctx *ctx, ftv_voter_db *db, const ftv_vote_desc *desc, const int32_t *memory,
+                    int32_t out_memory, uint32_t avoid, uint32_t flags, void *stream, ftv_place_report *rep);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,7 @@ this package; the GPU library never does, and the two share no code.
 The definitions follow the paper's statement of the voter (Kicherer & Karl,
 Sec. IV-D): integer values are compared bit-wise, floating-point values are
 equal when they differ by no more than a programmer-set maximum, and the voter
-returns the presumable correct result of the duplicated task runs.
+decides which of the duplicated task runs' results is to be taken as correct.
 """
 from __future__ import annotations
 

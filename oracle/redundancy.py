@@ -11,7 +11,7 @@ What the paper fixes:
     runs t; the fault-aware runtime is F = R * t / v (R with no history,
     infinite when v = 0 < t);
   * a task is duplicated onto the combinations with the lowest fault-aware
-    runtime and the voter determines the presumable correct result;
+    runtime and the voter decides which result is taken as correct;
   * a run that reports a direct fault (an API error) is abandoned, its data
     invalid, and execution restarts with the next best combination;
   * a run that does not finish within its profiled runtime times a
@@ -29,7 +29,13 @@ Readings where the paper is silent (the library's):
     of its valid runs' times; an UNRESOLVED vote counts nothing and the next
     attempt re-ranks;
   * a timeout applies only to a unit with a profile (R > 0 and v > 0); its
-    limit is R * factor.
+    limit is R * factor;
+  * check intervals (the paper: a unit with p = 1 is only used in predefined
+    check intervals): with an interval N > 0, each attempt passes over the
+    units with F = inf outside its k best runs and counts one more skip for
+    each; the first such unit (in rank order) whose count would reach N runs
+    instead as an extra replica of the attempt, voted and counted like the
+    others; a unit that runs has its count reset.
 """
 from __future__ import annotations
 
@@ -46,6 +52,7 @@ class Unit:
     runtime: float
     valid: int = 0
     total: int = 0
+    skipped: int = 0
 
 
 def fault_aware(u: Unit) -> float:
@@ -73,7 +80,7 @@ class Report:
     consensus: object = None
 
 
-def run_redundant(impl_units, units, k, max_attempts, timeout_factor, tol, behave):
+def run_redundant(impl_units, units, k, max_attempts, timeout_factor, tol, behave, check_interval=0):
     """impl_units[i]: unit of implementation i; units: list of Unit (updated in
     place); behave(attempt, impl) -> (kind, result array, seconds): OK with
     its result and run time, ERROR, or SLOW (would exceed any timeout; its
@@ -83,7 +90,26 @@ def run_redundant(impl_units, units, k, max_attempts, timeout_factor, tol, behav
     for a in range(max_attempts):
         f = [fault_aware(units[impl_units[i]]) for i in range(len(impl_units))]
         order = sorted(range(len(impl_units)), key=lambda i: (f[i], i))
-        chosen = [i for i in order if i not in failed_impls][:k]
+        alive = [i for i in order if i not in failed_impls]
+        chosen = alive[:k]
+        if check_interval:
+            seen = set()
+            for i in chosen:
+                seen.add(impl_units[i])
+                units[impl_units[i]].skipped = 0
+            extra = None
+            for i in alive[k:]:
+                u = units[impl_units[i]]
+                if impl_units[i] in seen or not math.isinf(fault_aware(u)):
+                    continue
+                seen.add(impl_units[i])
+                if extra is None and u.skipped + 1 >= check_interval:
+                    extra = i
+                    u.skipped = 0
+                else:
+                    u.skipped += 1
+            if extra is not None and 2 <= len(chosen) < 7:
+                chosen.append(extra)
         if len(chosen) < 2:
             break
         survivors, failed_now = [], []

@@ -17,9 +17,10 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(ROOT, "_build", "ftv")
 LIB = os.path.join(PKG, "libftv.so")
 
-SOURCES = ["ftv_vote_f32.hip", "ftv_vote_f64.hip", "ftv_vote_i32.hip", "ftv_vote_i64.hip", "ftv_vote_batch.hip", "ftv_vote_noalloc.hip",
+SOURCES = ["ftv_vote_f32.hip", "ftv_vote_f64.hip", "ftv_vote_i32.hip", "ftv_vote_i64.hip", "ftv_vote_batch.hip",
+           "ftv_vote_noalloc.hip",
            "ftv_blocks.hip", "ftv_copy.hip", "ftv_api.cpp", "ftv_server.cpp", "ftv_units.cpp", "ftv_mm.cpp",
-           "ftv_run.cpp"]
+           "ftv_run.cpp", "ftv_host.cpp", "ftv_place.cpp"]
 
 ARCH = "gfx950"
 # -ffp-contract=off and no flush-to-zero: the relative tolerance test must be
@@ -28,7 +29,7 @@ ARCH = "gfx950"
 DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
                 "-fno-gpu-flush-denormals-to-zero", "-Wall", "-Wno-unused-function",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-D__HIP_PLATFORM_AMD__"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-D__HIP_PLATFORM_AMD__", "-fopenmp"]
 
 
 def _hipcc() -> str:
@@ -59,7 +60,7 @@ def build(jobs: int = 4) -> str:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     # only the C ABI (ftv_*) is exported; internal C++ symbols stay local
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread",
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread", "-fopenmp",
            f"-Wl,--version-script={os.path.join(CSRC, 'ftv.map')}"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

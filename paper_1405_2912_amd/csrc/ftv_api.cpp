@@ -155,6 +155,16 @@ struct ftv_ctx {
   hipEvent_t mem_done{};
   hipStream_t mem_stream{};
   bool mem_pending = false;
+  // ftv_vote_blocks without caller fingerprints: the fingerprints of every
+  // replica's blocks (pass 1 writes them, pass 2 votes them).  A call on
+  // another stream than the last one waits for it; a grown buffer's
+  // predecessor is freed with the context (the last call may still read it).
+  uint64_t *blk_fps = nullptr;
+  uint64_t blk_fps_cap = 0;  // words
+  std::vector<void *> retired;
+  hipEvent_t blk_done{};
+  hipStream_t blk_stream{};
+  bool blk_pending = false;
   // kernel timing (ftv_ctx_set_timing): a pair of events around the vote
   // kernel of each ftv_vote and the persistent kernel of each ftv_vote_batch
   bool timing = false;
@@ -545,6 +555,9 @@ int ftv_ctx_destroy(ftv_ctx *c) {
     (void)hipStreamDestroy(c->copy_stream);
   }
   if (c->stage) (void)hipFree(c->stage);
+  if (c->blk_fps) (void)hipFree(c->blk_fps);
+  for (void *p : c->retired) (void)hipFree(p);
+  if (c->blk_done) (void)hipEventDestroy(c->blk_done);
   delete c;
   return FTV_OK;
 }
@@ -863,11 +876,36 @@ int ftv_vote_blocks(ftv_ctx *c, const void *const *replicas, uint32_t k, int32_t
   b.mask = mask;
   b.bstats = bstats;
   uint64_t *slot = nullptr;
-  rc = stream_slot(c, (hipStream_t)stream, &slot);
+  hipStream_t s = (hipStream_t)stream;
+  rc = stream_slot(c, s, &slot);
   if (rc) return rc;
   b.acc = slot + kNumCounters;
-  hipError_t e = launch_vote_blocks(b, c->num_cus, (hipStream_t)stream);
+  const bool own_fps = !fps && nblocks;
+  if (own_fps) {
+    if (!c->blk_done) HIPCHK(hipEventCreateWithFlags(&c->blk_done, hipEventDisableTiming));
+    if (c->blk_pending && c->blk_stream != s) HIPCHK(hipStreamWaitEvent(s, c->blk_done, 0));
+    const uint64_t words = (uint64_t)k * nblocks;
+    if (words > c->blk_fps_cap) {
+      uint64_t cap = 1ull << 16;
+      while (cap < words) cap <<= 1;
+      void *p = nullptr;
+      if (hipMalloc(&p, cap * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FTV_E_NOMEM, "cannot allocate the block fingerprints");
+      }
+      if (c->blk_fps) c->retired.push_back(c->blk_fps);
+      c->blk_fps = (uint64_t *)p;
+      c->blk_fps_cap = cap;
+    }
+    b.fps = c->blk_fps;
+  }
+  hipError_t e = launch_vote_blocks(b, c->num_cus, s);
   if (e != hipSuccess) return hip_fail(e, "block vote kernel launch");
+  if (own_fps) {
+    HIPCHK(hipEventRecord(c->blk_done, s));
+    c->blk_stream = s;
+    c->blk_pending = true;
+  }
   return FTV_OK;
 }
 

@@ -6,28 +6,30 @@
 // are combined pairwise, level by level, a node being FNV-1a over the two words
 // (left, right).
 //
-// Whole blocks: one workgroup of T = min(512, BB/64) threads per block walks
+// Whole blocks: one workgroup of T = min(256, BB/64) threads per block walks
 // it in sub-chunks of 64*T bytes (one leaf per thread).  The sub-chunk is
 // read with fully coalesced 16-byte loads (chunk c*T + t to thread t, so each
 // load instruction of a wave covers 1 KiB of consecutive bytes), transposed
 // through LDS (double-buffered, XOR-swizzled so that neither the writes nor
 // the leaf-major reads conflict on banks) so that thread t then holds leaf t.
 // The first six tree levels are combined across the lanes of a wave, the next
-// (up to three) over the wave roots in LDS, the last (up to two) over the
+// (up to two) over the wave roots in LDS, the last (up to two) over the
 // sub-chunk roots.  The loads of the next sub-chunk are in flight while the
 // current one is hashed.  Reading each lane's own 64-byte leaf directly from
 // HBM instead (lanes 64 bytes apart in every load) measured 1.6x slower.
 //
-// Block vote: the same workgroup hashes the block in all k replicas, votes
-// the k fingerprints by exact equality and restores the consensus from the
-// lowest-indexed replica holding a strict-majority fingerprint.  Replica 0's
-// data is streamed into the consensus while it is hashed, so in the common
-// case (replica 0 agrees with the majority) the restore costs one write pass
-// and no extra read.  A second kernel scans the block map: it counts the
-// map's statistics per workgroup and runs the element vote over every block
-// without a majority; a one-workgroup finalize kernel writes the stats.  No
-// kernel of the three waits on another's workgroups: kernel boundaries on
-// the stream order them.
+// Block vote, two passes.  Pass 1 fingerprints every block of every replica,
+// replica after replica, so the chip streams one replica at a time (on
+// MI355X five replicas read at the same offsets together streamed about 15%
+// slower than one after another); replica 0's data is streamed into the
+// consensus while it is hashed.  Pass 2 votes the k fingerprints of each
+// block by exact equality, writes the block map and its counts, re-copies
+// the blocks whose strict-majority fingerprint is not replica 0's from the
+// lowest-indexed replica holding it (in the common case replica 0 agrees and
+// the restore cost one write pass and no extra read), and runs the element
+// vote over every block without a majority; a one-workgroup finalize kernel
+// writes the stats.  No kernel waits on another's workgroups: kernel
+// boundaries on the stream order them.
 //
 // A partial last block (the buffer ends inside it) is handled by one
 // workgroup of BB/64 threads reading its leaves directly, with zero padding.
@@ -132,13 +134,9 @@ __device__ __forceinline__ const void *rep_ptr(const BlockVoteD &b, int r) {
 }
 
 // ---- whole blocks: coalesced loads transposed through LDS -----------------
-// Threads per whole-block workgroup.  The block vote (k reads, a consensus
-// and a mask write) is fastest with 512 (a 32 KiB sub-chunk per step, its LDS
-// tile double-buffered in 64 KiB, two workgroups per CU): 2.58 ms for the
-// k = 5 fp64 16384^2 checkpoint against 2.66 ms with 256 and 2.72 ms with
-// 1024.  The read-only fingerprint pass is fastest with 256 (0.33 ms for a
-// 2 GiB buffer against 0.40 ms with 512).
-constexpr uint32_t kVoteT = 512;
+// Threads per whole-block workgroup: 256 (a 16 KiB sub-chunk per step, its
+// LDS tile double-buffered in 32 KiB).  The read-only fingerprint pass of a
+// 2 GiB buffer takes 0.33 ms with 256 threads against 0.40 ms with 512.
 constexpr uint32_t kFingerprintT = 256;
 
 // LDS slot of 16-byte chunk g of a sub-chunk.  Thread t writes chunks c*T + t
@@ -269,39 +267,22 @@ __device__ __forceinline__ uint32_t vote_fps(const uint64_t (&f)[K], int *src_ou
   return bm;
 }
 
-// Pass 1 over whole blocks: fingerprints of the block in all k replicas, their
-// vote, the block map, and the restore.  Only a block whose majority
-// fingerprint differs from replica 0's is copied again, from the source
-// replica.  Blocks without a majority are left to pass 2, which rewrites their
-// consensus and mask.
-template <int K>
-__global__ __launch_bounds__(kVoteT) void k_vote_blocks(BlockVoteD b) {
-  __shared__ u32x4 lbuf[2][4 * kVoteT];
-  __shared__ uint64_t sw[kVoteT / 64];
-  __shared__ uint64_t sroot[K][4];
-  const uint64_t blk = blockIdx.x;
-  const Walk w = make_walk(blk, b.block_bytes);
-  walk_block<K, true, kVoteT>(b, w, lbuf, sw, sroot);
-  if (threadIdx.x < (uint32_t)K) {
-    const uint32_t r = threadIdx.x;
-    const uint64_t f = lds_tree(sroot[r], w.nsub);
-    sroot[r][0] = f;
-    if (b.fps) b.fps[(uint64_t)r * b.nblocks + blk] = f;
-  }
-  __syncthreads();
-  uint64_t f[K];
-#pragma unroll
-  for (int r = 0; r < K; ++r) f[r] = sroot[r][0];
-  int src = 0;
-  const uint32_t bm = vote_fps<K>(f, &src);
-  if (!(bm & 0x80u) && (bm & 1u)) {  // replica 0 is not the majority: recopy
-    const u32x4 *sp = reinterpret_cast<const u32x4 *>(
-        reinterpret_cast<const uint8_t *>(rep_ptr<K>(b, src)) + w.boff);
-    const uintptr_t dp = reinterpret_cast<uintptr_t>(b.cons) + w.boff;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(b.block_bytes / 16); i += w.nth)
-      stream_store16(dp, i * 16u, ld16(sp, i));
-  }
-  if (threadIdx.x == 0) b.blockmap[blk] = (uint8_t)bm;
+// Pass 1 over whole blocks: the fingerprints of every whole block of the k
+// replicas, one workgroup per (block, replica), dispatched replica after
+// replica (blockIdx.y outer), so that the chip streams one replica at a time;
+// the workgroups of replica 0 also stream its data into the consensus and
+// zero the mask bytes of its elements.  The vote of the fingerprints, the
+// block map and the re-copy of blocks where replica 0 is outvoted are pass 2's.
+__global__ __launch_bounds__(kFingerprintT) void k_hash_replicas(BlockVoteD b) {
+  __shared__ u32x4 lbuf[2][4 * kFingerprintT];
+  __shared__ uint64_t sw[kFingerprintT / 64];
+  __shared__ uint64_t sroot[1][4];
+  BlockVoteD one = b;
+  one.rep[0] = rep_ptr<FTV_MAX_K>(b, (int)blockIdx.y);
+  const Walk w = make_walk(blockIdx.x, b.block_bytes);
+  if (blockIdx.y == 0) walk_block<1, true, kFingerprintT>(one, w, lbuf, sw, sroot);
+  else walk_block<1, false, kFingerprintT>(one, w, lbuf, sw, sroot);
+  if (threadIdx.x == 0) b.fps[(uint64_t)blockIdx.y * b.nblocks + blockIdx.x] = lds_tree(sroot[0], w.nsub);
 }
 
 // ---- the partial last block: one leaf per thread, read directly ------------
@@ -378,10 +359,13 @@ __global__ __launch_bounds__(1024) void k_vote_block_partial(BlockVoteD b, uint6
   if (threadIdx.x == 0) b.blockmap[blk] = (uint8_t)bm;
 }
 
-// Pass 2: scan of the block map in chunks of `chunk` blocks (at most the
-// workgroup size, one byte per thread): the map's counts, and the element vote
-// over every block without a fingerprint majority, which the workgroup runs
-// block by block.  Per workgroup the non-zero counts go to the accumulators.
+// Pass 2: the vote of the fingerprints, in chunks of `chunk` blocks (at most
+// the workgroup size, one block per thread): the block map and its counts, the
+// re-copy of every whole block whose majority fingerprint is not replica 0's
+// (from the lowest replica holding it), and the element vote over every block
+// without a fingerprint majority; the workgroup runs the copies and the
+// element votes block by block.  Per workgroup the non-zero counts go to the
+// accumulators.
 // The workgroup is wide (1024 threads, several vectors per lane for small k)
 // so that a 64 KiB block takes one or two passes: a lone no-majority block is
 // a latency chain of passes, not a bandwidth problem.
@@ -399,12 +383,15 @@ __global__ __launch_bounds__(kScanThreads) void k_blocks_scan(BlockVoteD b, uint
   __shared__ uint64_t sh[16 * kNumCounters];
   __shared__ uint32_t s_cnt[kBlkAcc];
   __shared__ uint32_t s_nfb;
+  __shared__ uint32_t s_ncp;
   __shared__ uint64_t s_list[kScanThreads];
+  __shared__ uint64_t s_copy[kScanThreads];  // block | source replica << 56
   // the block's task record lives in LDS: a local record indexed at run time
   // (the rare general vote does) would be placed in scratch memory
   __shared__ TaskD t;
   const uint64_t per = b.block_bytes / sizeof(W);
   const uint64_t n = b.nbytes / sizeof(W);
+  const uint64_t nwhole = b.nbytes / b.block_bytes;
   if (threadIdx.x < (uint32_t)kBlkAcc) s_cnt[threadIdx.x] = 0;
   uint32_t c_dis = 0, c_fb = 0, c_rep[K];
 #pragma unroll
@@ -413,16 +400,37 @@ __global__ __launch_bounds__(kScanThreads) void k_blocks_scan(BlockVoteD b, uint
   acc.zero();
   for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < b.nblocks; base += (uint64_t)gridDim.x * chunk) {
     const uint64_t blk = base + threadIdx.x;
-    const uint32_t bm = (threadIdx.x < chunk && blk < b.nblocks) ? b.blockmap[blk] : 0u;
+    uint32_t bm = 0;
+    int src = 0;
+    if (threadIdx.x < chunk && blk < b.nblocks) {
+      uint64_t f[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) f[r] = b.fps[(uint64_t)r * b.nblocks + blk];
+      bm = vote_fps<K>(f, &src);
+      b.blockmap[blk] = (uint8_t)bm;
+    }
     c_dis += (bm & 0x7fu) != 0;
     c_fb += bm >> 7;
 #pragma unroll
     for (int r = 0; r < K; ++r) c_rep[r] += (bm >> r) & 1u;
-    if (!__syncthreads_or((int)(bm & 0x80u))) continue;
-    if (threadIdx.x == 0) s_nfb = 0;
+    // replica 0 outvoted in a whole block (the partial block restores itself)
+    const bool recopy = !(bm & 0x80u) && (bm & 1u) && blk < nwhole;
+    if (!__syncthreads_or((int)((bm & 0x80u) || recopy))) continue;
+    if (threadIdx.x == 0) s_nfb = s_ncp = 0;
     __syncthreads();
     if (bm & 0x80u) s_list[atomicAdd(&s_nfb, 1u)] = blk;
+    if (recopy) s_copy[atomicAdd(&s_ncp, 1u)] = blk | ((uint64_t)src << 56);
     __syncthreads();
+    const uint32_t ncp = s_ncp;
+    for (uint32_t i = 0; i < ncp; ++i) {
+      const uint64_t cb = s_copy[i] & ((1ull << 56) - 1);
+      const int from = (int)(s_copy[i] >> 56);
+      const u32x4 *sp = reinterpret_cast<const u32x4 *>(
+          reinterpret_cast<const uint8_t *>(rep_ptr<K>(b, from)) + cb * b.block_bytes);
+      const uintptr_t dp = reinterpret_cast<uintptr_t>(b.cons) + cb * b.block_bytes;
+      for (uint32_t v = threadIdx.x; v < (uint32_t)(b.block_bytes / 16); v += kScanThreads)
+        stream_store16(dp, v * 16u, ld16(sp, v));
+    }
     const uint32_t nfb = s_nfb;
     for (uint32_t i = 0; i < nfb; ++i) {
       const uint64_t e0 = s_list[i] * per;
@@ -532,7 +540,8 @@ template <int K>
 hipError_t launch_blocks_hash(const BlockVoteD &b, hipStream_t s) {
   const uint64_t nwhole = b.nbytes / b.block_bytes;
   if (nwhole) {
-    hipLaunchKernelGGL((k_vote_blocks<K>), dim3((uint32_t)nwhole), dim3(block_threads(b.block_bytes, kVoteT)), 0, s, b);
+    hipLaunchKernelGGL(k_hash_replicas, dim3((uint32_t)nwhole, (uint32_t)K),
+                       dim3(block_threads(b.block_bytes, kFingerprintT)), 0, s, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

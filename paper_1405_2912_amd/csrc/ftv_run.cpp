@@ -122,7 +122,6 @@ int ftv_run_redundant(ftv_ctx *ctx, const ftv_impl *impls, uint32_t nimpl, ftv_u
   if (cfg->max_attempts < 1) return fail(FTV_E_INVALID, "max_attempts must be >= 1");
   if (!(cfg->timeout_factor >= 0) || std::isinf(cfg->timeout_factor))
     return fail(FTV_E_INVALID, "timeout_factor must be finite and >= 0");
-  if (cfg->reserved != 0) return fail(FTV_E_INVALID, "reserved must be 0");
   int rc = check_tol(cfg->dtype, cfg->tol);
   if (rc) return rc;
   if (nimpl < 2) return fail(FTV_E_INVALID, "at least two implementations are needed");
@@ -173,7 +172,33 @@ int ftv_run_redundant(ftv_ctx *ctx, const ftv_impl *impls, uint32_t nimpl, ftv_u
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
       return fault_aware(units[impls[a].unit]) < fault_aware(units[impls[b].unit]);
     });
-    if (order.size() > cfg->k) order.resize(cfg->k);
+    // check intervals: units with F = +infinity outside the k best are passed
+    // over; the first one due runs as an extra replica
+    if (cfg->check_interval) {
+      std::vector<char> seen(nunits, 0);
+      const size_t kk = std::min<size_t>(cfg->k, order.size());
+      for (size_t j = 0; j < kk; ++j) {
+        ftv_unit &u = units[impls[order[j]].unit];
+        seen[impls[order[j]].unit] = 1;
+        u.skipped = 0;
+      }
+      int extra = -1;
+      for (size_t j = kk; j < order.size(); ++j) {
+        const uint32_t ui = impls[order[j]].unit;
+        ftv_unit &u = units[ui];
+        if (seen[ui] || !std::isinf(fault_aware(u))) continue;
+        seen[ui] = 1;
+        if (extra < 0 && u.skipped + 1 >= cfg->check_interval) {
+          extra = (int)order[j];
+          u.skipped = 0;
+        } else {
+          u.skipped += 1;
+        }
+      }
+      order.resize(kk);
+      if (extra >= 0 && order.size() < FTV_MAX_K && order.size() >= 2) order.push_back((uint32_t)extra);
+    }
+    if (order.size() > cfg->k + (cfg->check_interval ? 1u : 0u)) order.resize(cfg->k);
     if (order.size() < 2) break;
     rep->attempts++;
     // launch every chosen implementation into a replica of its own

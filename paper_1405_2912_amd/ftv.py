@@ -18,8 +18,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libftv.so")
 
 # ---- constants mirrored from include/ftv.h ---------------------------------
-OK, E_INVALID, E_DTYPE, E_K, E_ALIGN, E_HIP, E_NOMEM, E_BUSY, E_NOTREADY, E_CLOSED = \
-    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+OK, E_INVALID, E_DTYPE, E_K, E_ALIGN, E_HIP, E_NOMEM, E_BUSY, E_NOTREADY, E_CLOSED, E_MISMATCH = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
 F32, F64, I32, I64 = 0, 1, 2, 3
 TOL_EXACT, TOL_ULP, TOL_REL = 0, 1, 2
 UNANIMOUS, TASK_MAJORITY, ELEMENT_MAJORITY, UNRESOLVED = 0, 1, 2, 3
@@ -27,6 +27,9 @@ MAX_K = 7
 MASK_NOMAJ = 0x80
 NOALLOC_MAX_TASKS = 4096
 REQ_VOTE, REQ_FINGERPRINT = 0, 1
+VOTER_HOST1, VOTER_HOSTMT, VOTER_GPU = 0, 1, 2
+NUM_VOTERS = 3
+PLACE_REDUNDANT = 1
 
 
 class FtvError(RuntimeError):
@@ -91,7 +94,7 @@ class ServerStats(Structure):
 
 
 class Unit(Structure):
-    _fields_ = [("runtime", c_double), ("valid", c_uint64), ("total", c_uint64)]
+    _fields_ = [("runtime", c_double), ("valid", c_uint64), ("total", c_uint64), ("skipped", c_uint64)]
 
 
 class SiblingInfo(Structure):
@@ -109,13 +112,18 @@ class Impl(Structure):
 
 class RedundancyCfg(Structure):
     _fields_ = [("k", c_uint32), ("max_attempts", c_uint32), ("timeout_factor", c_double),
-                ("dtype", c_int32), ("reserved", c_uint32), ("tol", Tol)]
+                ("dtype", c_int32), ("check_interval", c_uint32), ("tol", Tol)]
 
 
 class RedundancyReport(Structure):
     _fields_ = [("attempts", c_uint32), ("verdict", c_int32), ("timeouts", c_uint32),
                 ("errors", c_uint32), ("winner_unit", c_uint32), ("reserved", c_uint32),
                 ("seconds", c_double)]
+
+
+class PlaceReport(Structure):
+    _fields_ = [("unit", c_int32 * 3), ("runs", c_uint32), ("result_unit", c_int32), ("agreed", c_int32),
+                ("probed", c_uint32), ("reserved", c_uint32), ("seconds", c_double * 3)]
 
 
 class MMCheckResult(Structure):
@@ -130,7 +138,9 @@ EXPORTS = ["ftv_version", "ftv_last_error", "ftv_now_ns", "ftv_ctx_create", "ftv
            "ftv_server_destroy", "ftv_fault_aware_runtime", "ftv_rank_units", "ftv_record_vote",
            "ftv_mm_create", "ftv_mm_destroy", "ftv_mm_register", "ftv_mm_request", "ftv_mm_release",
            "ftv_mm_siblings", "ftv_mm_check", "ftv_run_redundant", "ftv_vote_mem",
-           "ftv_ctx_set_timing", "ftv_ctx_kernel_times", "ftv_vote_batch_noalloc"]
+           "ftv_ctx_set_timing", "ftv_ctx_kernel_times", "ftv_vote_batch_noalloc", "ftv_vote_host",
+           "ftv_voter_db_create", "ftv_voter_db_destroy", "ftv_voter_db_profile", "ftv_voter_db_inject",
+           "ftv_vote_placed"]
 
 _lib = None
 
@@ -188,6 +198,13 @@ def load():
     L.ftv_mm_check.argtypes = [vp, c_uint32, c_uint64, vp, POINTER(MMCheckResult)]
     L.ftv_run_redundant.argtypes = [vp, POINTER(Impl), c_uint32, POINTER(Unit), c_uint32,
                                     POINTER(RedundancyCfg), c_uint64, vp, POINTER(RedundancyReport)]
+    L.ftv_vote_host.argtypes = [POINTER(VoteDesc), c_uint32]
+    L.ftv_voter_db_create.argtypes = [c_uint32, c_uint32, POINTER(vp)]
+    L.ftv_voter_db_destroy.argtypes = [vp]
+    L.ftv_voter_db_profile.argtypes = [vp, c_uint32, c_uint64, c_uint32, c_int32, POINTER(Unit)]
+    L.ftv_voter_db_inject.argtypes = [vp, c_uint32, c_uint32]
+    L.ftv_vote_placed.argtypes = [vp, vp, POINTER(VoteDesc), POINTER(c_int32), c_int32, c_uint32, c_uint32, vp,
+                                  POINTER(PlaceReport)]
     for name in EXPORTS:
         fn = getattr(L, name, None)
         if fn is not None and name not in ("ftv_version", "ftv_last_error", "ftv_now_ns",
@@ -681,9 +698,119 @@ class MemoryManager:
             pass
 
 
+# ---- the voter on the host's cores and its placement -------------------------
+def _stats_dict(s: Stats) -> dict:
+    return {"pair": np.array(s.pair, dtype=np.uint64).reshape(7, 7),
+            "disagree": np.array(s.disagree, dtype=np.uint64), "no_majority": int(s.no_majority),
+            "n": int(s.n), "verdict": int(s.verdict), "winner": int(s.winner)}
+
+
+def vote_host(replicas, tol: Tol, threads: int = 1, want_consensus: bool = True, want_mask: bool = True):
+    """ftv_vote_host on k C-contiguous numpy arrays of one dtype (host memory);
+    returns (consensus, mask, stats dict).  threads: 1 = one thread, 0 = every core."""
+    if not 1 <= len(replicas) <= MAX_K:
+        _bad(f"1 to {MAX_K} replicas")
+    x0 = replicas[0]
+    codes = {np.dtype(np.float32): F32, np.dtype(np.float64): F64, np.dtype(np.int32): I32,
+             np.dtype(np.int64): I64}
+    if x0.dtype not in codes:
+        _bad(f"unsupported dtype {x0.dtype}")
+    n = x0.size
+    for r, a in enumerate(replicas):
+        if not isinstance(a, np.ndarray) or not a.flags["C_CONTIGUOUS"]:
+            _bad(f"replica {r} must be a C-contiguous numpy array")
+        if a.dtype != x0.dtype or a.size < n:
+            _bad(f"replica {r} must have dtype {x0.dtype} and at least {n} elements")
+    cons = np.empty(n, dtype=x0.dtype) if want_consensus else None
+    mask = np.empty(n, dtype=np.uint8) if want_mask else None
+    st = Stats()
+    d = VoteDesc()
+    for r, a in enumerate(replicas):
+        d.replicas[r] = a.ctypes.data
+    d.k, d.dtype, d.n, d.tol = len(replicas), codes[x0.dtype], n, tol
+    d.consensus = cons.ctypes.data if cons is not None else None
+    d.mask = mask.ctypes.data if mask is not None else None
+    d.stats = ctypes.addressof(st)
+    _check(load().ftv_vote_host(ctypes.byref(d), int(threads)))
+    return cons, mask, _stats_dict(st)
+
+
+class VoterDB:
+    """Performance database of the voter units (the C calls ftv_voter_db_*)."""
+
+    def __init__(self, check_interval: int = 8, host_threads: int = 0):
+        h = c_void_p()
+        _check(load().ftv_voter_db_create(int(check_interval), int(host_threads), ctypes.byref(h)))
+        self.handle = h
+
+    def profile(self, unit: int, nbytes: int, host_mask: int, out_memory: int) -> Unit:
+        u = Unit()
+        _check(load().ftv_voter_db_profile(self.handle, int(unit), int(nbytes), int(host_mask),
+                                           int(out_memory), ctypes.byref(u)))
+        return u
+
+    def inject(self, unit: int, count: int):
+        _check(load().ftv_voter_db_inject(self.handle, int(unit), int(count)))
+
+    def close(self):
+        if self.handle:
+            load().ftv_voter_db_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def vote_placed(ctx: Context, db: VoterDB, replicas, tol: Tol, out_memory: int = MEM_DEVICE, consensus=None,
+                mask=None, stats=None, avoid: int = 0, redundant: bool = False, stream=None,
+                want_consensus: bool = True, want_mask: bool = True):
+    """ftv_vote_placed: replicas are torch tensors in host memory (CPU) or on the
+    GPU; outputs lie in out_memory.  Returns (consensus, mask, stats, report)."""
+    torch = _torch()
+    n, dev = _check_replicas(replicas, host_ok=True)
+    if dev is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    odev = dev if out_memory == MEM_DEVICE else torch.device("cpu")
+    x0 = replicas[0]
+    for name, t in (("consensus", consensus), ("mask", mask), ("stats", stats)):
+        if t is not None and t.is_cuda != (out_memory == MEM_DEVICE):
+            _bad(f"{name} must lie in out_memory")
+    if consensus is not None:
+        _check_tensor(consensus, "consensus", device=dev if odev.type == "cuda" else None, dtype=x0.dtype,
+                      min_numel=n, host_ok=True)
+    if mask is not None:
+        _check_tensor(mask, "mask", device=dev if odev.type == "cuda" else None, dtype=torch.uint8, min_numel=n,
+                      host_ok=True)
+    if stats is not None:
+        _check_tensor(stats, "stats", device=dev if odev.type == "cuda" else None,
+                      min_bytes=ctypes.sizeof(Stats), host_ok=True)
+    if consensus is None and want_consensus:
+        consensus = torch.empty(n, dtype=x0.dtype, device=odev)
+    if mask is None and want_mask:
+        mask = torch.empty(n, dtype=torch.uint8, device=odev)
+    if stats is None:
+        stats = torch.zeros(ctypes.sizeof(Stats) // 8, dtype=torch.int64, device=odev)
+    d = make_desc(replicas, tol, n=n, host_ok=True)
+    d.consensus = consensus.data_ptr() if consensus is not None else None
+    d.mask = mask.data_ptr() if mask is not None else None
+    d.stats = stats.data_ptr()
+    mem = (c_int32 * len(replicas))(*[MEM_DEVICE if r.is_cuda else MEM_HOST for r in replicas])
+    rep = PlaceReport()
+    _check(load().ftv_vote_placed(ctx.handle, db.handle, ctypes.byref(d), mem, int(out_memory), int(avoid),
+                                  PLACE_REDUNDANT if redundant else 0, c_void_p(_stream_handle(stream)),
+                                  ctypes.byref(rep)))
+    report = {"units": [int(u) for u in rep.unit[:rep.runs]], "result_unit": int(rep.result_unit),
+              "agreed": bool(rep.agreed), "probed": bool(rep.probed),
+              "seconds": [float(x) for x in rep.seconds[:rep.runs]]}
+    return consensus, mask, stats, report
+
+
 # ---- redundant execution with timeouts and retries ----------------------------
 def run_redundant(ctx: Context, impls, units, out, tol: Tol, k: int = 2, max_attempts: int = 3,
-                  timeout_factor: float = 0.0) -> dict:
+                  timeout_factor: float = 0.0, check_interval: int = 0) -> dict:
     """impls: list of (fn, unit) where fn(out_ptr: int, stream_ptr: int) -> int
     enqueues the task into the device buffer at out_ptr on the HIP stream
     stream_ptr and returns 0 (non-zero: a direct fault).  units: a ctypes array
@@ -700,7 +827,7 @@ def run_redundant(ctx: Context, impls, units, out, tol: Tol, k: int = 2, max_att
         keep.append(c)
         return c
     arr = (Impl * len(impls))(*[Impl(wrap(fn), None, int(u), 0) for fn, u in impls])
-    cfg = RedundancyCfg(int(k), int(max_attempts), float(timeout_factor), dtype_code(out), 0, tol)
+    cfg = RedundancyCfg(int(k), int(max_attempts), float(timeout_factor), dtype_code(out), int(check_interval), tol)
     rep = RedundancyReport()
     _check(load().ftv_run_redundant(ctx.handle, arr, len(impls), units, len(units),
                                     ctypes.byref(cfg), out.numel(), c_void_p(out.data_ptr()),

@@ -51,21 +51,23 @@ class Impls:
         return run
 
 
-def _call(gpu, ctx, impls, units_lib, units_model, impl_units, k, attempts, factor, results):
+def _call(gpu, ctx, impls, units_lib, units_model, impl_units, k, attempts, factor, results, check_interval=0):
     import torch
     out = torch.empty(N, dtype=torch.float32, device="cuda")
     rep = gpu.run_redundant(ctx, [(impls.fn(i), impl_units[i]) for i in range(len(impl_units))],
-                            units_lib, out, gpu.exact(), k=k, max_attempts=attempts, timeout_factor=factor)
+                            units_lib, out, gpu.exact(), k=k, max_attempts=attempts, timeout_factor=factor,
+                            check_interval=check_interval)
     torch.cuda.synchronize()
 
     def behave(a, i):
         b = impls.behaviour[i]
         return (b, results[impls.result[i]] if b != ERROR else None, 0.0)
-    want = run_redundant(impl_units, units_model, k, attempts, factor, oracle.exact(), behave)
+    want = run_redundant(impl_units, units_model, k, attempts, factor, oracle.exact(), behave, check_interval)
     assert rep["attempts"] == len(want.attempts)
     assert rep["verdict"] == want.verdict
     assert (rep["errors"], rep["timeouts"]) == (want.errors, want.timeouts)
-    assert [(u.valid, u.total) for u in units_lib] == [(u.valid, u.total) for u in units_model]
+    assert [(u.valid, u.total, u.skipped) for u in units_lib] == \
+        [(u.valid, u.total, u.skipped) for u in units_model]
     if want.verdict != oracle.UNRESOLVED:
         assert rep["winner_unit"] == want.winner_unit
         assert np.array_equal(out.cpu().numpy().view(np.uint32), want.consensus.view(np.uint32))
@@ -153,3 +155,21 @@ def test_random_calls_match_the_model(gpu, ctx):
         k = int(rng.choice([2, 3]))
         print(f"case: random call {call}: behaviour={impls.behaviour} results={impls.result} k={k}", flush=True)
         _call(gpu, ctx, impls, units_lib, units_model, impl_units, k, 3, 0.0, results)
+
+
+def test_check_interval_retries_a_failed_unit(gpu, ctx):
+    """A unit whose every run failed (F infinite) is passed over and re-tried
+    as an extra replica every third attempt; while its results are wrong it is
+    outvoted, and once it returns good results it regains a finite F --
+    profiles, skip counts, verdicts and consensus call by call equal to the
+    model's."""
+    results = _results()
+    impls = Impls(gpu, results)
+    impl_units = [0, 1, 2]
+    units_lib, units_model = _setup(gpu, [1e-3, 2e-3, 5e-4], [(0, 0), (0, 0), (0, 2)])
+    impls.behaviour = [OK, OK, OK]
+    for call in range(7):
+        impls.result = [0, 0, 1 if call < 3 else 0]      # unit 2 recovers after its first re-try
+        print(f"case: check interval 3, call {call}, unit 2 result {impls.result[2]}", flush=True)
+        _call(gpu, ctx, impls, units_lib, units_model, impl_units, 2, 1, 0.0, results, check_interval=3)
+    assert units_lib[2].valid >= 1 and gpu.fault_aware_runtime(units_lib[2]) < float("inf")

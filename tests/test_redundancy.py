@@ -97,3 +97,47 @@ def test_fewer_than_two_left_ends_the_call():
     rep = run_redundant([0, 1, 2], units, 2, 5, 0.0, oracle.exact(), lambda a, i: (ERROR, None, 0.0))
     # the first attempt loses both runs; one implementation is left: no second attempt
     assert len(rep.attempts) == 1 and rep.errors == 2 and rep.verdict == oracle.UNRESOLVED
+
+
+def test_check_interval_retries_a_failed_unit_and_it_recovers():
+    """Sec. IV-B: a unit with fault probability 1 (F infinite) is used only at
+    check intervals.  With an interval of 3 it is passed over twice, then runs
+    as an extra replica; it has recovered, so its run is valid and F is finite
+    again.  Without check intervals it is never run again."""
+    good = _vals(6)
+    beh = {0: (OK, good, 1.0), 1: (OK, good, 1.0), 2: (OK, good, 0.5)}
+    units = [Unit(1.0), Unit(1.0), Unit(0.5, 0, 2)]
+    chosen = []
+    for _ in range(4):
+        rep = run_redundant([0, 1, 2], units, 2, 1, 0.0, oracle.exact(), lambda a, i: beh[i], check_interval=3)
+        chosen.append(rep.attempts[0].chosen)
+        assert rep.verdict == oracle.UNANIMOUS
+    assert chosen[:3] == [[0, 1], [0, 1], [0, 1, 2]]
+    assert (units[2].valid, units[2].total) == (1, 3) and fault_aware(units[2]) == 1.5
+    assert chosen[3] == [0, 1]          # F = 1.5 now ranks it third, and finite: no more re-try
+    units = [Unit(1.0), Unit(1.0), Unit(0.5, 0, 2)]
+    for _ in range(5):
+        rep = run_redundant([0, 1, 2], units, 2, 1, 0.0, oracle.exact(), lambda a, i: beh[i])
+        assert rep.attempts[0].chosen == [0, 1]
+    assert fault_aware(units[2]) == math.inf
+
+
+def test_check_interval_still_faulty_unit_is_outvoted_and_retried_again():
+    good = _vals(7)
+    bad = good.copy()
+    bad[100] = 9.0
+    beh = {0: (OK, good, 1.0), 1: (OK, good, 1.0), 2: (OK, bad, 0.5)}
+    units = [Unit(1.0), Unit(1.0), Unit(0.5, 0, 1)]
+    chosen = []
+    for _ in range(4):
+        rep = run_redundant([0, 1, 2], units, 2, 1, 0.0, oracle.exact(), lambda a, i: beh[i], check_interval=2)
+        chosen.append(rep.attempts[0].chosen)
+        assert np.array_equal(rep.consensus, good)
+    assert chosen == [[0, 1], [0, 1, 2], [0, 1], [0, 1, 2]]
+    assert (units[2].valid, units[2].total) == (0, 3) and fault_aware(units[2]) == math.inf
+    # a probe that fails directly counts as a run that was not valid as well
+    beh[2] = (ERROR, None, 0.0)
+    units = [Unit(1.0), Unit(1.0), Unit(0.5, 0, 1)]
+    rep = run_redundant([0, 1, 2], units, 2, 1, 0.0, oracle.exact(), lambda a, i: beh[i], check_interval=1)
+    assert rep.attempts[0].chosen == [0, 1, 2] and rep.errors == 1 and rep.verdict == oracle.UNANIMOUS
+    assert (units[2].valid, units[2].total) == (0, 2)
