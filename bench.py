@@ -31,6 +31,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote_task.hpp", "paper_1405_2912_amd/csrc/ftv_vote_f32.hip",
                   "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
 BATCH_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote_batch.hip", "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
+BLOCK_SOURCES = ["paper_1405_2912_amd/csrc/ftv_blocks.hip", "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
 
 
 def log(*a):
@@ -60,7 +61,9 @@ def traffic_from_profile(name: str, launches_bytes_alg: float, sources=None):
         return None
     if d.get("kernel_hash") != kernel_hash(sources):
         return None
-    return d.get("hbm_bytes_per_launch")
+    if "hbm_bytes_per_launch" in d:
+        return d["hbm_bytes_per_launch"]
+    return d.get("hbm_bytes_per_call")   # every kernel of one call, summed
 
 
 def cpu_model() -> str:
@@ -331,7 +334,11 @@ def check_batch_task(ftv, tasks, descs, cons, mask, stats, i) -> bool:
                 (ref.no_majority, ref.verdict, ref.winner, t["n"]))
 
 
-def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10):
+def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10, schedule=None):
+    """Batched vs per-task launches on the uneven workload.  schedule: None =
+    the autotuner picks it; else (tile_vecs, block, grid_mult, order,
+    nt_stores), used as given (so that a profile holds launches at one
+    schedule only)."""
     import ctypes
     import numpy as np
     import torch
@@ -341,8 +348,12 @@ def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10):
     cons_b, mask_b, st_b, descs_b = output_set(ftv, tasks, out_sizes)
     cons_p, mask_p, st_p, descs_p = output_set(ftv, tasks, out_sizes)
     torch.cuda.synchronize()
-    log("bench: autotuning the batched schedule")
-    best = ftv.tune_batch(ctx, descs_b, iters=2)
+    if schedule is None:
+        log("bench: autotuning the batched schedule")
+        best = ftv.tune_batch(ctx, descs_b, iters=2)
+    else:
+        best = ftv.BatchCfg(*schedule, 0)
+        ctx.set_batch_config(best)
     torch.cuda.synchronize()
     log("bench: timing batched launches")
     ftv.vote_batch(ctx, descs_b)
@@ -389,7 +400,8 @@ def bench_batched(ftv, ctx, ntasks=4096, reps_timed=10):
                         "unit": "GB/s", "frac": round(alg / kern_ms / 1e6 / HBM_PEAK_GBS, 4),
                         "traffic": traffic_from_profile("vote_batch_4096_uneven_counters.json", alg,
                                                         BATCH_SOURCES),
-                        "kernel": "k_vote_batch (tuned schedule)", "alg_bytes_per_launch": alg,
+                        "kernel": "k_vote_batch (%s schedule)" % ("tuned" if schedule is None else "given"),
+                        "alg_bytes_per_launch": alg,
                         "kernel_ms": round(kern_ms, 4), "kernel_ms_min": round(min(kern), 4),
                         "kernel_ms_max": round(max(kern), 4), "launches": len(kern)},
            "speedup": round(per_task_ms / batched_ms, 3),
@@ -441,11 +453,15 @@ def bench_blocks(ftv, ctx, side=16384, reps_timed=10):
     s = ftv.read_block_stats(out["bstats"])
     nblocks = n // per
     alg = 5 * n * 8 + n * 8 + n + 5 * nblocks * 8 + nblocks
+    traffic = traffic_from_profile("block_vote_k5_f64_16384sq_counters.json", alg, BLOCK_SOURCES)
     restored = bool(torch.equal(out["consensus"].view(torch.int64), reps[0].view(torch.int64)))
     res = {"workload": f"k=5 fp64 {side}x{side} checkpoint, 64 KiB blocks, stuck words, flips, a shifted "
                        f"replica, one forced no-majority block",
            "ms": round(ms, 4), "replica_gbps": round(5 * n * 8 / ms / 1e6, 1),
            "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4), "alg_bytes": alg,
+           "roofline": {"bound": "hbm", "achieved": round(alg / ms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "kernel": "k_hash_replicas + k_blocks_scan + k_blocks_finalize (one call)"},
            "blocks": s["blocks"], "disagree_blocks": s["disagree_blocks"],
            "fallback_blocks": s["fallback_blocks"], "unresolved_elems": s["unresolved_elems"],
            "verdict": s["verdict"], "consensus_equals_clean_replica": restored,
@@ -531,9 +547,12 @@ def bench_mixed(ftv, ctx, side=16384, reps_timed=3, chunk_mib=64):
     mask = torch.empty(n, dtype=torch.uint8, device="cuda")
     st = ftv.stats_tensor("cuda")
     tol = ftv.ulp(4)
-    out = {"workload": f"k=3 fp32 {side}x{side} (1 GiB per replica), replica 1 in host memory, "
-                       f"{chunk_mib} MiB pieces"}
-    ref = None
+    out = {"workload": f"k=3 fp32 {side}x{side} (1 GiB per replica), replica 1 in host memory "
+                       f"(pinned: read in place by the vote kernel; pageable: {chunk_mib} MiB staged pieces)"}
+    ftv.vote(ctx, reps, tol, cons, mask, st)
+    torch.cuda.synchronize()
+    ref = (cons.clone(), mask.clone(), st.clone())
+    same = True
     for kind in ("pinned", "pageable"):
         host = torch.empty(n, dtype=torch.float32, pin_memory=(kind == "pinned"))
         host.copy_(reps[1])
@@ -546,6 +565,7 @@ def bench_mixed(ftv, ctx, side=16384, reps_timed=3, chunk_mib=64):
             ftv.vote_mem(ctx, mixed, tol, cons, mask, st, chunk_bytes=chunk_mib << 20)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / reps_timed * 1e3
+        same = same and all(torch.equal(a, b) for a, b in zip(ref, (cons, mask, st)))
         dev = torch.empty_like(reps[1])
         dev.copy_(host, non_blocking=True)
         torch.cuda.synchronize()
@@ -554,18 +574,12 @@ def bench_mixed(ftv, ctx, side=16384, reps_timed=3, chunk_mib=64):
             dev.copy_(host, non_blocking=True)
         torch.cuda.synchronize()
         copy_ms = (time.perf_counter() - t0) / reps_timed * 1e3
-        if ref is None:
-            ftv.vote(ctx, reps, tol, cons, mask, st)
-            torch.cuda.synchronize()
-            ref = st.clone()
-            ftv.vote_mem(ctx, mixed, tol, cons, mask, st, chunk_bytes=chunk_mib << 20)
-            torch.cuda.synchronize()
         out[kind] = {"ms": round(ms, 3), "host_replica_gbps": round(n * 4 / ms / 1e6, 1),
                      "h2d_copy_ms": round(copy_ms, 3), "h2d_copy_gbps": round(n * 4 / copy_ms / 1e6, 1),
                      "vote_over_copy": round(ms / copy_ms, 3)}
         del host, dev
-    out["stats_equal_all_device_vote"] = bool(torch.equal(ref, st))
-    del reps, cons, mask
+    out["results_equal_all_device_vote"] = bool(same)
+    del reps, cons, mask, ref
     torch.cuda.empty_cache()
     return out
 
@@ -625,6 +639,18 @@ def bench_placement(ftv, ctx, runs=5):
         gpu_from = next((r["bytes_per_replica"] for r in rs if r["fastest"] == "gpu"), None)
         mt_from = next((r["bytes_per_replica"] for r in rs if r["fastest"] == "host_all_cores"), None)
         cross[where] = {"all_cores_fastest_from_bytes": mt_from, "gpu_fastest_from_bytes": gpu_from}
+    # each unit with the data in its own memory (no transfers), as the paper's figure compares them
+    own = []
+    for nbytes in sizes:
+        h = next(r for r in rows if r["data"] == "host" and r["bytes_per_replica"] == nbytes)
+        d = next(r for r in rows if r["data"] == "device" and r["bytes_per_replica"] == nbytes)
+        t = {"host_1_thread": h["host_1_thread_us"], "host_all_cores": h["host_all_cores_us"], "gpu": d["gpu_us"]}
+        own.append({"bytes_per_replica": nbytes, **{k + "_us": v for k, v in t.items()},
+                    "fastest": min((v, k) for k, v in t.items())[1]})
+    cross["data_in_each_units_memory"] = {
+        "rows": own,
+        "all_cores_fastest_from_bytes": next((r["bytes_per_replica"] for r in own if r["fastest"] == "host_all_cores"), None),
+        "gpu_fastest_from_bytes": next((r["bytes_per_replica"] for r in own if r["fastest"] == "gpu"), None)}
     torch.cuda.empty_cache()
     return {"workload": "k=3 fp32 replicas (the parity recipe) of 1 KiB .. 64 MiB each, ULP 4; per unit the "
                         "median of %d runs, transfers of replicas and outputs included" % runs,
@@ -797,6 +823,8 @@ def main():
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
+    ap.add_argument("--batch-schedule", default=None,
+                    help="tile_vecs,block,grid_mult,order,nt_stores for the batched section (default: autotuned)")
     ap.add_argument("--only", choices=["batched", "blocks", "mixed", "ramp", "placement"],
                     help="run only this workload and print its result (for profiling its kernels)")
     args = ap.parse_args()
@@ -817,7 +845,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.only:
-        run = {"batched": lambda: bench_batched(ftv, ctx, args.batch_tasks),
+        sched = tuple(int(x) for x in args.batch_schedule.split(",")) if args.batch_schedule else None
+        run = {"batched": lambda: bench_batched(ftv, ctx, args.batch_tasks, schedule=sched),
                "blocks": lambda: bench_blocks(ftv, ctx),
                "mixed": lambda: bench_mixed(ftv, ctx),
                "ramp": lambda: bench_serving_ramp(ftv, ctx),

@@ -172,15 +172,17 @@ int ftv_ctx_kernel_times(ftv_ctx *ctx, float *ms, uint32_t cap, uint32_t *count)
  * one in device memory (Sec. IV-D), and where the results lie decides what a
  * vote costs (Sec. V-A).  memory[r] (HOST array of k) is FTV_MEM_HOST or
  * FTV_MEM_DEVICE and says where replicas[r] lies; consensus, mask and stats
- * are device memory as for ftv_vote.  Host replicas are streamed in pieces of
- * chunk_bytes per replica (rounded down to 4096 elements; in [1 MiB, 4 GiB])
- * through two device staging sets of the context on a copy stream, each
- * piece voted as soon as it has arrived while the next one is copied; the
- * counts of all pieces form one stats record.  Results are identical to
- * ftv_vote on device copies of the same replicas.  Host replicas in pinned
- * memory (hipHostMalloc) copy at the full link rate; pageable ones go through
- * the runtime's own staging.  Host replicas must stay unchanged until the
- * stream has been synchronised.  No host replica (or n = 0): exactly ftv_vote.
+ * are device memory as for ftv_vote.  A host replica in page-locked memory
+ * mapped into the device's address space (hipHostMalloc, PyTorch's pinned
+ * tensors; the runtime's pointer attributes decide) is read by the vote
+ * kernel in place, over the link, with no staging.  Pageable host replicas
+ * are streamed in pieces of chunk_bytes per replica (rounded down to 4096
+ * elements; in [1 MiB, 4 GiB]) through two device staging sets of the
+ * context on a copy stream, each piece voted as soon as it has arrived while
+ * the next one is copied; the counts of all pieces form one stats record.
+ * Results are identical to ftv_vote on device copies of the same replicas.
+ * Host replicas must stay unchanged until the stream has been synchronised.
+ * No pageable host replica (or n = 0): one ftv_vote.
  * Errors: those of ftv_vote, FTV_E_INVALID (memory flag, chunk_bytes),
  * FTV_E_NOMEM (staging), FTV_E_HIP. */
 int ftv_vote_mem(ftv_ctx *ctx, const ftv_vote_desc *desc, const int32_t *memory, uint64_t chunk_bytes,

@@ -441,6 +441,36 @@ void cache_store(const std::string &path, const std::string &key, const ftv_batc
 }
 
 // The pieces of an ftv_vote_mem call: copy, vote without finalizing.
+// Device-visible address of a host replica the GPU can read in place:
+// page-locked memory mapped into the device's address space (hipHostMalloc,
+// PyTorch's pinned tensors) whose whole range [p, p + bytes) lies in one
+// allocation.  nullptr for pageable memory or whatever the runtime does not
+// report as such an allocation.
+const void *mapped_host(const void *p, uint64_t bytes) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (a.type != hipMemoryTypeHost) return nullptr;
+  void *base = nullptr;
+  size_t size = 0;
+  if (hipPointerGetAttribute(&base, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, (hipDeviceptr_t)p) != hipSuccess ||
+      hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const char *b = static_cast<const char *>(base), *q = static_cast<const char *>(p);
+  if (!b || q < b || bytes > size || (uint64_t)(q - b) > size - bytes) return nullptr;
+  hipPointerAttribute_t ab;
+  if (hipPointerGetAttributes(&ab, base) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (ab.type != hipMemoryTypeHost || !ab.devicePointer || ab.hostPointer != base) return nullptr;
+  return static_cast<const char *>(ab.devicePointer) + (q - b);
+}
+
 int mem_pieces(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, const TaskD &t, const VoteWs &ws,
                bool vec, uint64_t es, uint64_t chunk, uint64_t set_bytes, uint32_t nhost, hipStream_t s) {
   const uint64_t n = desc->n;
@@ -623,13 +653,32 @@ int ftv_vote_mem(ftv_ctx *c, const ftv_vote_desc *desc, const int32_t *memory, u
   TaskD t;
   int rc = make_task(desc, false, &t);
   if (rc) return rc;
-  uint32_t nhost = 0;
-  for (uint32_t r = 0; r < desc->k; ++r) {
+  for (uint32_t r = 0; r < desc->k; ++r)
     if (memory[r] != FTV_MEM_HOST && memory[r] != FTV_MEM_DEVICE)
       return fail(FTV_E_INVALID, "memory[r] must be FTV_MEM_HOST or FTV_MEM_DEVICE");
-    nhost += memory[r] == FTV_MEM_HOST;
+  if (desc->n == 0) return ftv_vote(c, desc, stream);
+  // host replicas the device can read in place (pinned, mapped) are voted
+  // there, over the link; only pageable ones go through the staging sets
+  ftv_vote_desc dd = *desc;
+  int32_t mem[FTV_MAX_K];
+  uint32_t nhost = 0;
+  const uint64_t rbytes = desc->n * (uint64_t)elem_size(desc->dtype);
+  for (uint32_t r = 0; r < desc->k; ++r) {
+    mem[r] = memory[r];
+    if (memory[r] != FTV_MEM_HOST) continue;
+    const void *m = mapped_host(desc->replicas[r], rbytes);
+    if (m) {
+      dd.replicas[r] = m;
+      mem[r] = FTV_MEM_DEVICE;
+    } else {
+      ++nhost;
+    }
   }
-  if (nhost == 0 || desc->n == 0) return ftv_vote(c, desc, stream);
+  if (nhost == 0) return ftv_vote(c, &dd, stream);
+  desc = &dd;
+  memory = mem;
+  rc = make_task(desc, false, &t);
+  if (rc) return rc;
   if (chunk_bytes < (1u << 20) || chunk_bytes > (1ull << 32))
     return fail(FTV_E_INVALID, "chunk_bytes must be in [1 MiB, 4 GiB]");
   // the staged pieces are aligned, so every piece takes the vector path when
