@@ -733,31 +733,52 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
     arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
     outstanding = []
     max_out = 0
+    # where the time of a request goes: arrival -> submit -> admit -> done
+    phases = {"submit_after_arrival_us": [], "admit_after_submit_us": [], "done_after_admit_us": []}
+
+    def record(res):
+        phases["submit_after_arrival_us"].append((res.t_submit_ns - res.t_arrival_ns) / 1e3)
+        phases["admit_after_submit_us"].append((res.t_admit_ns - res.t_submit_ns) / 1e3)
+        phases["done_after_admit_us"].append((res.t_done_ns - res.t_admit_ns) / 1e3)
+
+    def poll_release(tk, wait):
+        res = srv.poll(tk, wait)
+        if res is None:
+            return False
+        record(res)
+        srv.release(tk)
+        return True
+
     for i in range(count):
         ta = int(arrivals[i])
+        # the request is described before it is due (the task that produces it
+        # knows its outputs); at its arrival time it is only handed over
+        n, o = int(sizes[i]), offs[i]
+        reps = [p[o:o + n] for p in pool]
+        c = m = None
+        if i in pick:
+            c = torch.empty(n, dtype=torch.float32, device="cuda")
+            m = torch.empty(n, dtype=torch.uint8, device="cuda")
+        req = srv.vote_request(reps, tol, c, m, n=n)
+        req.t_arrival_ns = ta
         while True:
             now = ftv.now_ns()
             if now >= ta:
                 break
             # release finished requests while waiting for the next arrival
-            while outstanding and srv.poll(outstanding[0], 0) is not None:
-                srv.release(outstanding.pop(0))
+            while outstanding and poll_release(outstanding[0], 0):
+                outstanding.pop(0)
             if ta - ftv.now_ns() > 200_000:
                 time.sleep(0.0001)
-        n, o = int(sizes[i]), offs[i]
-        reps = [p[o:o + n] for p in pool]
         if i in pick:
-            c = torch.empty(n, dtype=torch.float32, device="cuda")
-            m = torch.empty(n, dtype=torch.uint8, device="cuda")
-            held[i] = (srv.submit_vote(reps, tol, c, m, t_arrival_ns=ta, n=n, inputs_ready=True), c, m)
+            held[i] = (srv.submit(req), c, m)
             continue
-        outstanding.append(srv.submit_vote(reps, tol, t_arrival_ns=ta, n=n, inputs_ready=True))
+        outstanding.append(srv.submit(req))
         max_out = max(max_out, len(outstanding))
-        if len(outstanding) > 64 and srv.poll(outstanding[0], 0) is not None:
-            srv.release(outstanding.pop(0))
+        if len(outstanding) > 64 and poll_release(outstanding[0], 0):
+            outstanding.pop(0)
     for tk in outstanding:
-        srv.poll(tk, -1)
-        srv.release(tk)
+        poll_release(tk, -1)
     st = srv.stats()
     checked = ok = 0
     if held:
@@ -766,6 +787,7 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
         host_pool = [p.cpu().numpy() for p in pool]
         for i, (tk, c, m) in sorted(held.items()):
             res = srv.poll(tk, -1)
+            record(res)
             n, o = int(sizes[i]), offs[i]
             ref, _ = oracle.vote_threads([hp[o:o + n] for hp in host_pool], oracle.ulp(4))
             s = ftv.result_stats(res)
@@ -793,6 +815,7 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
             "max_requests_per_iteration": int(st["max_requests_per_iteration"]),
             "served_replica_gbps": round(st["replica_gbps"], 2),
             "peak_bytes_in_flight": int(st["peak_bytes_in_flight"]),
+            "median_phases_us": {k: round(float(np.median(v)), 1) for k, v in phases.items() if v},
             "oracle_sampled_ok": f"{ok}/{checked}" if checked else None,
             "oracle_sampled_largest_elems": largest if checked else None}
 
@@ -825,7 +848,7 @@ def main():
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
     ap.add_argument("--batch-schedule", default=None,
                     help="tile_vecs,block,grid_mult,order,nt_stores for the batched section (default: autotuned)")
-    ap.add_argument("--only", choices=["batched", "blocks", "mixed", "ramp", "placement"],
+    ap.add_argument("--only", choices=["batched", "blocks", "mixed", "ramp", "placement", "small", "serving"],
                     help="run only this workload and print its result (for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -850,7 +873,9 @@ def main():
                "blocks": lambda: bench_blocks(ftv, ctx),
                "mixed": lambda: bench_mixed(ftv, ctx),
                "ramp": lambda: bench_serving_ramp(ftv, ctx),
-               "placement": lambda: bench_placement(ftv, ctx)}[args.only]
+               "placement": lambda: bench_placement(ftv, ctx),
+               "small": lambda: bench_small(ftv, ctx),
+               "serving": lambda: bench_serving(ftv, ctx, args.serve_seconds, n_span=4, n_rand=12)}[args.only]
         res = run()
         ctx.close()
         print(json.dumps({args.only: res}), flush=True)

@@ -93,9 +93,10 @@ struct BatchLaunch {
 hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchLaunch &b, hipStream_t s);
-// Serving: zero queue_head and the accumulators of slots[0..hdr[2]).
+// Serving: zero queue_head; for slots[0..hdr[2]) copy their task records
+// newt[i] to tasks[slots[i]] and zero their accumulators.
 hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const uint32_t *slots,
-                             const uint64_t *hdr, hipStream_t s);
+                             const uint64_t *hdr, const TaskD *newt, TaskD *tasks, hipStream_t s);
 // Serving: stats records of the nfin slots listed in fin (host count).
 hipError_t launch_slots_finalize(const TaskD *tasks, const uint64_t *acc, const uint32_t *fin,
                                  uint32_t nfin, hipStream_t s);

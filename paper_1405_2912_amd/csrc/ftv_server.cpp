@@ -12,7 +12,11 @@
 // counts live in slot accumulators that persist across iterations; after the
 // iteration that issues a request's last tile, a small finalize kernel writes
 // its stats record straight into host-mapped memory, and the server thread
-// observes completion through the iteration's event.  Latency is measured from the request's scheduled arrival time.
+// observes completion through the iteration's event.  While iterations are in
+// flight, and for a millisecond after its last work, the server thread spins
+// (polling events and the queue) instead of sleeping, so completions and new
+// requests are seen within microseconds; an idle server waits on a condition
+// variable.  Latency is measured from the request's scheduled arrival time.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,10 +38,12 @@ using namespace ftv;
 
 namespace {
 
-constexpr uint32_t kTileVecs = 4096;       // 64 KiB per replica per tile
+constexpr uint32_t kTileVecs = 4096;       // largest tile: 64 KiB per replica
+constexpr uint32_t kMinTileVecs = 512;     // smallest tile: one step of a 256-thread workgroup
 constexpr uint64_t kMaxIterTiles = 65536;  // tiles per iteration table
 constexpr int kRing = 2;                   // iterations in flight
 constexpr uint64_t kGranule = 256;
+constexpr int64_t kSpinNs = 1000000;      // the server thread spins for 1 ms after its last work
 
 // First-fit allocator over one device allocation (256-byte granules).
 struct Arena {
@@ -103,6 +109,7 @@ struct Req {
   uint64_t in_bytes = 0, out_bytes = 0, replica_bytes = 0;
   int slot = -1;
   uint64_t nvec = 0;
+  uint32_t tile_vecs = kTileVecs;
   uint32_t ntiles = 0, issued = 0;
   bool new_slot = false;
   void *cons = nullptr;
@@ -119,7 +126,9 @@ struct Req {
 struct Iter {
   hipEvent_t ev{};
   bool busy = false;
-  char *h_buf = nullptr;  // [hdr 256 B][new slots u32 x max_slots][finishing slots u32 x max_slots][tiles]
+  // [hdr 256 B][new slots u32 x max_slots][finishing slots u32 x max_slots]
+  // [task records of the new slots][tiles]
+  char *h_buf = nullptr;
   char *d_buf = nullptr;
   uint32_t *d_queue = nullptr;
   std::vector<uint64_t> finishing;
@@ -153,6 +162,7 @@ struct ftv_server {
   uint64_t shared_iters = 0, max_reqs_iter = 0;
   double q_integral = 0;
   int64_t q_last_t = 0, t_first = 0, t_last_done = 0;
+  int64_t t_active = 0;  // last time the server thread admitted, launched or completed work
   uint64_t replica_bytes_done = 0;
   std::vector<double> lat_us;
 };
@@ -160,7 +170,21 @@ struct ftv_server {
 namespace {
 
 size_t iter_bytes(const ftv_server *s) {
-  return 256 + 2 * sizeof(uint32_t) * s->cfg.max_slots + sizeof(TileD) * kMaxIterTiles;
+  return 256 + 2 * sizeof(uint32_t) * s->cfg.max_slots + sizeof(TaskD) * s->cfg.max_slots +
+         sizeof(TileD) * kMaxIterTiles;
+}
+
+// Tile size of a request: as small as one workgroup step, as large as 64 KiB
+// per replica, and just large enough that the request alone fills the
+// iteration's grid once (3 workgroups per CU).  A small request is then spread
+// over many workgroups that each take one short tile -- its latency is a few
+// load round trips instead of the sixteen steps of one 64 KiB tile -- while a
+// large one keeps long tiles and few queue operations.
+uint32_t request_tile_vecs(uint64_t nvec, int num_cus) {
+  const uint64_t wgs = 3ull * (uint64_t)num_cus;
+  uint64_t t = (nvec + wgs - 1) / wgs;
+  t = (t + kMinTileVecs - 1) / kMinTileVecs * kMinTileVecs;
+  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(t, kMinTileVecs), kTileVecs);
 }
 
 void note_queue(ftv_server *s, int64_t now) {
@@ -212,7 +236,8 @@ void admit(ftv_server *s) {
       TaskD t;
       (void)make_task(&d, true, &t);  // validated by ftv_submit
       r.nvec = t.nvec;
-      r.ntiles = (uint32_t)std::max<uint64_t>(1, (t.nvec + kTileVecs - 1) / kTileVecs);
+      r.tile_vecs = request_tile_vecs(t.nvec, s->num_cus);
+      r.ntiles = (uint32_t)std::max<uint64_t>(1, (t.nvec + r.tile_vecs - 1) / r.tile_vecs);
       t.ntiles = r.ntiles;
       s->h_tasks[slot] = t;
       r.new_slot = true;
@@ -245,27 +270,32 @@ int launch_iteration(ftv_server *s, Iter &it) {
   const size_t slots_bytes = sizeof(uint32_t) * s->cfg.max_slots;
   uint32_t *hs = reinterpret_cast<uint32_t *>(it.h_buf + 256);
   uint32_t *hf = reinterpret_cast<uint32_t *>(it.h_buf + 256 + slots_bytes);
-  TileD *ht = reinterpret_cast<TileD *>(it.h_buf + 256 + 2 * slots_bytes);
-  const uint64_t chunk_tiles = std::max<uint64_t>(1, s->cfg.chunk_bytes / (16ull * kTileVecs));
+  TaskD *hn = reinterpret_cast<TaskD *>(it.h_buf + 256 + 2 * slots_bytes);
   uint64_t nnew = 0, nfin = 0, ntiles = 0, nreq = s->fp_wait.size();
+  for (uint64_t tk : s->active)
+    if (s->reqs[tk].new_slot) ++nnew;
+  // the tiles follow the new slots' task records
+  const size_t tiles_off = 256 + 2 * slots_bytes + (sizeof(TaskD) * nnew + 255) / 256 * 256;
+  TileD *ht = reinterpret_cast<TileD *>(it.h_buf + tiles_off);
+  nnew = 0;
   std::vector<uint64_t> still;
   for (uint64_t tk : s->active) {
     Req &r = s->reqs[tk];
     if (r.new_slot) {
       // the work that produces the request's replicas comes first
       if (r.rq.ready) HIPCHK(hipStreamWaitEvent(s->stream, (hipEvent_t)r.rq.ready, 0));
+      hn[nnew] = s->h_tasks[r.slot];
       hs[nnew++] = (uint32_t)r.slot;
-      HIPCHK(hipMemcpyAsync(s->d_tasks + r.slot, s->h_tasks + r.slot, sizeof(TaskD),
-                            hipMemcpyHostToDevice, s->stream));
       r.new_slot = false;
     }
+    const uint64_t chunk_tiles = std::max<uint64_t>(1, s->cfg.chunk_bytes / (16ull * r.tile_vecs));
     const uint64_t take = std::min<uint64_t>({chunk_tiles, (uint64_t)(r.ntiles - r.issued),
                                               kMaxIterTiles - ntiles});
     for (uint64_t j = r.issued; j < r.issued + take; ++j) {
       TileD &d = ht[ntiles++];
       d.task = (uint32_t)r.slot;
-      d.v0 = std::min<uint64_t>(j * kTileVecs, r.nvec);
-      d.v1 = std::min<uint64_t>((j + 1) * kTileVecs, r.nvec);
+      d.v0 = std::min<uint64_t>(j * r.tile_vecs, r.nvec);
+      d.v1 = std::min<uint64_t>((j + 1) * r.tile_vecs, r.nvec);
       d.last = (j + 1 == r.ntiles) ? 1u : 0u;
     }
     r.issued += (uint32_t)take;
@@ -282,16 +312,18 @@ int launch_iteration(ftv_server *s, Iter &it) {
   hdr[1] = s->cfg.max_slots;
   hdr[2] = nnew;
   hdr[3] = nfin;
-  const size_t bytes = 256 + 2 * slots_bytes + sizeof(TileD) * ntiles;
+  // one copy per iteration: header, slot lists, new task records and tiles
+  const size_t bytes = tiles_off + sizeof(TileD) * ntiles;
   HIPCHK(hipMemcpyAsync(it.d_buf, it.h_buf, bytes, hipMemcpyHostToDevice, s->stream));
   const uint64_t *d_hdr = reinterpret_cast<const uint64_t *>(it.d_buf);
   const uint32_t *d_slots = reinterpret_cast<const uint32_t *>(it.d_buf + 256);
   const uint32_t *d_fin = reinterpret_cast<const uint32_t *>(it.d_buf + 256 + slots_bytes);
-  HIPCHK(launch_slots_init(it.d_queue, s->d_acc, d_slots, d_hdr, s->stream));
+  const TaskD *d_new = reinterpret_cast<const TaskD *>(it.d_buf + 256 + 2 * slots_bytes);
+  HIPCHK(launch_slots_init(it.d_queue, s->d_acc, d_slots, d_hdr, d_new, s->d_tasks, s->stream));
   if (ntiles) {
     BatchLaunch b;
     b.tasks = s->d_tasks;
-    b.tiles = reinterpret_cast<const TileD *>(it.d_buf + 256 + 2 * slots_bytes);
+    b.tiles = reinterpret_cast<const TileD *>(it.d_buf + tiles_off);
     b.prefix = nullptr;  // table mode: the iteration lists its tiles
     b.tile_vecs = kTileVecs;
     b.ntiles_dev = d_hdr;
@@ -415,14 +447,17 @@ void server_main(ftv_server *s) {
       break;
     }
     if (broken && s->stop) break;
-    if (!progressed) {
-      if (busy) {
-        lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(10));
-        lk.lock();
-      } else {
-        s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
-      }
+    if (progressed) {
+      s->t_active = ftv_now_ns();
+    } else if (busy || ftv_now_ns() - s->t_active < kSpinNs) {
+      // iterations in flight, or work seen within the last millisecond: spin,
+      // so that a finished iteration or a new request is noticed within
+      // microseconds (a timed sleep of a few microseconds lasts tens of them)
+      lk.unlock();
+      for (int i = 0; i < 32; ++i) __builtin_ia32_pause();
+      lk.lock();
+    } else {
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
     }
   }
 }

@@ -122,15 +122,21 @@ __global__ __launch_bounds__(64) void k_batch_finalize(BatchLaunch b) {
     finalize_task(b.tasks[i], b.acc + i * kNumCounters, false, s_tot);
 }
 
-// Serving iterations: re-arm the tile queue and clear the accumulators of the
-// slots whose requests join in this iteration (slots[0..hdr[2]) ).
+// Serving iterations: re-arm the tile queue, and for the slots whose requests
+// join in this iteration (slots[0..hdr[2]) ) install their task records
+// (carried in the iteration's table) and clear their accumulators.
 __global__ __launch_bounds__(256) void k_slots_init(uint32_t *queue_head, uint64_t *acc,
-                                                    const uint32_t *slots, const uint64_t *hdr) {
+                                                    const uint32_t *slots, const uint64_t *hdr,
+                                                    const TaskD *newt, TaskD *tasks) {
+  static_assert(sizeof(TaskD) % 8 == 0, "task records are copied in 8-byte words");
+  constexpr uint64_t W = sizeof(TaskD) / 8;
   const uint64_t nnew = hdr[2];
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = gid; i < nnew * kNumCounters; i += stride)
     acc[(uint64_t)slots[i / kNumCounters] * kNumCounters + i % kNumCounters] = 0;
+  for (uint64_t i = gid; i < nnew * W; i += stride)
+    reinterpret_cast<uint64_t *>(tasks + slots[i / W])[i % W] = reinterpret_cast<const uint64_t *>(newt + i / W)[i % W];
   if (gid == 0) *queue_head = 0;
 }
 
@@ -174,8 +180,8 @@ hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s) {
 }
 
 hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const uint32_t *slots,
-                             const uint64_t *hdr, hipStream_t s) {
-  hipLaunchKernelGGL(k_slots_init, dim3(32), dim3(256), 0, s, queue_head, acc, slots, hdr);
+                             const uint64_t *hdr, const TaskD *newt, TaskD *tasks, hipStream_t s) {
+  hipLaunchKernelGGL(k_slots_init, dim3(32), dim3(256), 0, s, queue_head, acc, slots, hdr, newt, tasks);
   return hipGetLastError();
 }
 

@@ -546,14 +546,21 @@ class Server:
         req.ready = ev.cuda_event
         return ev
 
-    def submit_vote(self, replicas, tol: Tol, consensus=None, mask=None, t_arrival_ns: int = 0,
-                    user_tag: int = 0, n=None, stream=None, inputs_ready: bool = False) -> int:
-        """inputs_ready: the replicas are complete already (no event is passed)."""
+    @staticmethod
+    def vote_request(replicas, tol: Tol, consensus=None, mask=None, n=None, user_tag: int = 0) -> Request:
+        """A checked vote request (inputs complete, no ready event), to be
+        passed to submit() later -- e.g. prepared before the request is due."""
         req = Request()
         req.kind = REQ_VOTE
         req.vote = make_desc(replicas, tol, consensus, mask, None, n=n)
-        req.t_arrival_ns = int(t_arrival_ns)
         req.user_tag = int(user_tag)
+        return req
+
+    def submit_vote(self, replicas, tol: Tol, consensus=None, mask=None, t_arrival_ns: int = 0,
+                    user_tag: int = 0, n=None, stream=None, inputs_ready: bool = False) -> int:
+        """inputs_ready: the replicas are complete already (no event is passed)."""
+        req = self.vote_request(replicas, tol, consensus, mask, n=n, user_tag=user_tag)
+        req.t_arrival_ns = int(t_arrival_ns)
         ev = None if inputs_ready else self._ready(req, stream)
         return self.submit(req, ev)
 
