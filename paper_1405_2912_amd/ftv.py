@@ -777,14 +777,14 @@ def vote_placed(ctx: Context, db: VoterDB, replicas, tol: Tol, out_memory: int =
     """ftv_vote_placed: replicas are torch tensors in host memory (CPU) or on the
     GPU; outputs lie in out_memory.  Returns (consensus, mask, stats, report)."""
     torch = _torch()
+    for name, t in (("consensus", consensus), ("mask", mask), ("stats", stats)):
+        if t is not None and t.is_cuda != (out_memory == MEM_DEVICE):
+            _bad(f"{name} must lie in out_memory")
     n, dev = _check_replicas(replicas, host_ok=True)
     if dev is None:
         dev = torch.device("cuda", torch.cuda.current_device())
     odev = dev if out_memory == MEM_DEVICE else torch.device("cpu")
     x0 = replicas[0]
-    for name, t in (("consensus", consensus), ("mask", mask), ("stats", stats)):
-        if t is not None and t.is_cuda != (out_memory == MEM_DEVICE):
-            _bad(f"{name} must lie in out_memory")
     if consensus is not None:
         _check_tensor(consensus, "consensus", device=dev if odev.type == "cuda" else None, dtype=x0.dtype,
                       min_numel=n, host_ok=True)

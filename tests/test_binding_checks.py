@@ -92,3 +92,25 @@ def test_vote_mem_takes_host_replicas_but_device_outputs():
     h = torch.zeros(64)
     _raises(lambda: ftv.vote_mem(NoCtx(), [a, h], ftv.ulp(4), consensus=torch.zeros(64)), "consensus")
     _raises(lambda: ftv.vote_mem(NoCtx(), [a, torch.zeros(63)], ftv.ulp(4)), "replica 1 has 63")
+
+
+def test_vote_host_rejects_bad_arrays():
+    import numpy as np
+    a = np.zeros(100, dtype=np.float32)
+    with pytest.raises(ValueError):
+        ftv.vote_host([a, a[::2], a], ftv.ulp(4))                # not contiguous
+    with pytest.raises(ValueError):
+        ftv.vote_host([a, a.astype(np.float64), a], ftv.ulp(4))  # mixed dtypes
+    with pytest.raises(ValueError):
+        ftv.vote_host([a, a[:50], a], ftv.ulp(4))                # a replica too short
+    with pytest.raises(ValueError):
+        ftv.vote_host([a.astype(np.float16)] * 3, ftv.ulp(4))    # unsupported dtype
+    with pytest.raises(ValueError):
+        ftv.vote_host([a] * 8, ftv.ulp(4))                       # more than 7 replicas
+
+
+def test_vote_placed_rejects_outputs_in_the_wrong_memory():
+    a = torch.zeros(16)
+    with pytest.raises(ValueError):
+        ftv.vote_placed(NoCtx(), None, [a, a, a], ftv.ulp(4), out_memory=ftv.MEM_DEVICE,
+                        consensus=torch.zeros(16))               # a host tensor as device output

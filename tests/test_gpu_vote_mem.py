@@ -93,3 +93,30 @@ def test_reuse_empty_and_errors(gpu, ctx):
     reps = _place(small, ("host", "dev", "dev"))
     with pytest.raises(RuntimeError):
         gpu.vote_mem(ctx, reps, gpu.ulp(4), chunk_bytes=4096)
+
+
+def test_pinned_slices_read_in_place(gpu, ctx):
+    """Pinned host replicas are read by the vote kernel in place: replicas that
+    are slices of one pinned allocation, at element and 16-byte offsets (the
+    scalar and the vector path), equal the oracle and the all-device vote."""
+    import torch
+    rng = np.random.default_rng(77)
+    n = 200003
+    reps = _replicas(rng, np.float32, 3, n)
+    for off in (0, 1, 4):   # elements: 1 leaves the replicas 4-byte aligned only
+        pool = torch.empty(3 * (n + 8), dtype=torch.float32).pin_memory()
+        ts = []
+        for r in range(3):
+            base = r * (n + 8) + off
+            pool[base:base + n] = torch.from_numpy(reps[r])
+            ts.append(pool[base:base + n])
+        ts[1] = torch.from_numpy(reps[1]).cuda()     # one replica on the device
+        print(f"case: pinned slices of one allocation, offset {off}", flush=True)
+        ref = oracle.vote(reps, oracle.ulp(4))
+        cons, mask, st = gpu.vote_mem(ctx, ts, gpu.ulp(4), chunk_bytes=MIB)
+        torch.cuda.synchronize()
+        s = gpu.read_stats(st)
+        assert _same(cons.cpu().numpy(), ref.consensus)
+        assert np.array_equal(mask.cpu().numpy(), ref.mask)
+        assert np.array_equal(s["pair"][:3, :3], ref.pair) and np.array_equal(s["disagree"][:3], ref.disagree)
+        assert (s["no_majority"], s["verdict"], s["winner"]) == (ref.no_majority, ref.verdict, ref.winner)
