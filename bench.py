@@ -117,9 +117,12 @@ def cpu_baseline(reps_dev, single_elems: int, runs: int = 3):
 
 
 def main_vote(ftv, ctx, steps, warmup, side):
-    """The timed steps, with kernel timing on: per step the vote kernel's own
-    time (HIP events on the launch stream, recorded by the library around the
-    kernel) and the whole call's time (events around the call)."""
+    """The timed steps: `steps` back-to-back ftv_vote calls with nothing else
+    on the stream, synchronised on both sides (wall clock -> ms_per_step).
+    Then, outside the timed region, the same number of calls with kernel
+    timing on: per call the vote kernel's own time (HIP events the library
+    records on the launch stream around the kernel) and the whole call's time
+    (events around the call)."""
     import torch
     import synth.device as sd
     n = side * side
@@ -132,17 +135,20 @@ def main_vote(ftv, ctx, steps, warmup, side):
     for _ in range(warmup):
         ftv.vote(ctx, reps, tol, cons, mask, st)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     log(f"bench: timing {steps} steps")
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for _ in range(steps):
+        ftv.vote(ctx, reps, tol, cons, mask, st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"bench: kernel and call times of {steps} more calls")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ctx.set_timing(True)
     for i in range(steps):
         ev[i][0].record()
         ftv.vote(ctx, reps, tol, cons, mask, st)
         ev[i][1].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     kern = ctx.kernel_times()
     ctx.set_timing(False)
     call_ms = sum(a.elapsed_time(b) for a, b in ev) / steps

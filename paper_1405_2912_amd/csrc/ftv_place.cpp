@@ -415,11 +415,21 @@ int ftv_vote_placed(ftv_ctx *ctx, ftv_voter_db *db, const ftv_vote_desc *d, cons
   if (rc) return rc;
 
   // ---- redundant: a second voter, on the other device than the primary if possible ----
+  auto ran = [&](uint32_t u) {
+    for (uint32_t j = 0; j < rep->runs; ++j)
+      if (rep->unit[j] == (int32_t)u) return true;
+    return false;
+  };
   int second = -1;
   if (redundant) {
-    for (size_t i = next; i < usable.size() && second < 0; ++i)
-      if (on_host(usable[i]) != on_host(prim)) second = (int)usable[i];
-    for (size_t i = next; i < usable.size() && second < 0; ++i) second = (int)usable[i];
+    // preference: not avoided and on the other device; not avoided; avoided on the other device; any
+    for (int pass = 0; pass < 4 && second < 0; ++pass)
+      for (size_t i = next; i < usable.size() && second < 0; ++i) {
+        const uint32_t u = usable[i];
+        const bool ok_avoid = pass >= 2 || (allowed & (1u << u));
+        const bool ok_dev = (pass % 2) == 1 || on_host(u) != on_host(prim);
+        if (ok_avoid && ok_dev && !ran(u)) second = (int)u;
+      }
     if (second < 0 && probe >= 0) {
       second = probe;
       probe = -1;
@@ -443,7 +453,7 @@ int ftv_vote_placed(ftv_ctx *ctx, ftv_voter_db *db, const ftv_vote_desc *d, cons
       // a third voter settles it: a unit not run yet, or a due probe
       int third = -1;
       for (uint32_t u : usable)
-        if ((int)u != second && u != prim && third < 0) third = (int)u;
+        if (third < 0 && !ran(u)) third = (int)u;
       if (third < 0 && probe >= 0) {
         third = probe;
         probe = -1;
