@@ -707,11 +707,13 @@ def bench_redundant(ftv, ctx, side=16384, calls=7):
 # ---------------------------------------------------------------------------
 # serving: Poisson arrivals, continuous batching, p50/p99 latency
 # ---------------------------------------------------------------------------
-def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int = 128, count: int = None,
+def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int = 256, count: int = None,
                   n_span: int = 0, n_rand: int = 0):
     """chunk_mib: bytes per replica a request advances per iteration.  On
-    MI355X, 32 / 64 / 128 / 256 MiB gave p99 593 / 496 / 373 / 338 us at the
-    same p50 (97 us); 128 MiB keeps more iterations shared between requests."""
+    MI355X at 2000 req/s, 32 / 64 / 128 / 256 / 512 MiB gave p99 479 / 393 /
+    289 / 247 / 246 us at the same p50 (45-46 us): with 256 MiB every request
+    of this workload finishes in one iteration, and requests that arrive while
+    it runs are admitted into the next one (two iterations in flight)."""
     import numpy as np
     import torch
     import synth.device as sd
@@ -727,10 +729,10 @@ def bench_serving(ftv, ctx, seconds: float, rate: float = 2000.0, chunk_mib: int
     sizes = np.floor(np.exp(rng.uniform(np.log(4096), np.log(256 << 20), count)) / 4).astype(np.int64)
     offs = [int(rng.integers(0, (pool_elems - int(n)) // 64 + 1)) * 64 for n in sizes]
     tol = ftv.ulp(4)
-    # requests read back and checked against the oracle: the first n_span ones
-    # that span at least three iterations, and n_rand others at random; they
-    # get outputs of their own and are released only after the check
-    big = [i for i in range(count) if int(sizes[i]) * 4 > 2 * (chunk_mib << 20)][:n_span]
+    # requests read back and checked against the oracle: the n_span largest
+    # ones and n_rand others at random; they get outputs of their own and are
+    # released only after the check
+    big = sorted(range(count), key=lambda i: -int(sizes[i]))[:n_span]
     rest = [i for i in range(count) if i not in set(big)]
     pick = set(big) | set(np.random.default_rng(5).choice(rest, min(n_rand, len(rest)), replace=False).tolist())
     held = {}
@@ -849,6 +851,8 @@ def main():
     ap.add_argument("--main-only", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-chunk-mib", type=int, default=256,
+                    help="bytes per replica a served request advances per iteration")
     ap.add_argument("--batch-tasks", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain 1 GiB device copies (for HBM counter calibration)")
@@ -881,7 +885,8 @@ def main():
                "ramp": lambda: bench_serving_ramp(ftv, ctx),
                "placement": lambda: bench_placement(ftv, ctx),
                "small": lambda: bench_small(ftv, ctx),
-               "serving": lambda: bench_serving(ftv, ctx, args.serve_seconds, n_span=4, n_rand=12)}[args.only]
+               "serving": lambda: bench_serving(ftv, ctx, args.serve_seconds, chunk_mib=args.serve_chunk_mib,
+                                                n_span=4, n_rand=12)}[args.only]
         res = run()
         ctx.close()
         print(json.dumps({args.only: res}), flush=True)
@@ -931,7 +936,8 @@ def main():
         out["redundant"] = bench_redundant(ftv, ctx)
         out["placement"] = bench_placement(ftv, ctx)
         out["mixed_memory"] = bench_mixed(ftv, ctx)
-        out["serving"] = bench_serving(ftv, ctx, args.serve_seconds, n_span=4, n_rand=12)
+        out["serving"] = bench_serving(ftv, ctx, args.serve_seconds, chunk_mib=args.serve_chunk_mib, n_span=4,
+                                       n_rand=12)
         out["serving_ramp"] = bench_serving_ramp(ftv, ctx, min(2.0, args.serve_seconds))
     ctx.close()
     print(json.dumps(out), flush=True)
