@@ -93,10 +93,13 @@ struct BatchLaunch {
 hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch_vote(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchLaunch &b, hipStream_t s);
-// Serving: zero queue_head; for slots[0..hdr[2]) copy their task records
-// newt[i] to tasks[slots[i]] and zero their accumulators.
-hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const uint32_t *slots,
-                             const uint64_t *hdr, const TaskD *newt, TaskD *tasks, hipStream_t s);
+// Serving: copy the iteration table (table_bytes, 16-byte multiple) from pinned
+// host memory (a device-visible address) to table_d, zero queue_head, and for
+// slots_h[0..nnew) copy newt_h[i] to tasks[slots_h[i]] and zero their
+// accumulators (slots_h and newt_h: device-visible addresses in the host table).
+hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const void *table_h, void *table_d,
+                             uint64_t table_bytes, const uint32_t *slots_h, const TaskD *newt_h, uint64_t nnew,
+                             TaskD *tasks, hipStream_t s);
 // Serving: stats records of the nfin slots listed in fin (host count).
 hipError_t launch_slots_finalize(const TaskD *tasks, const uint64_t *acc, const uint32_t *fin,
                                  uint32_t nfin, hipStream_t s);

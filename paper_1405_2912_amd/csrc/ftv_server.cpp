@@ -129,6 +129,7 @@ struct Iter {
   // [hdr 256 B][new slots u32 x max_slots][finishing slots u32 x max_slots]
   // [task records of the new slots][tiles]
   char *h_buf = nullptr;
+  char *h_buf_dev = nullptr;  // the device's address of h_buf (pinned, mapped)
   char *d_buf = nullptr;
   uint32_t *d_queue = nullptr;
   std::vector<uint64_t> finishing;
@@ -169,8 +170,11 @@ struct ftv_server {
 
 namespace {
 
+// Bytes of an iteration table at most: header, two slot lists, the task
+// records of up to max_slots new requests (the tiles start at the next
+// 256-byte boundary after them) and kMaxIterTiles tiles.
 size_t iter_bytes(const ftv_server *s) {
-  return 256 + 2 * sizeof(uint32_t) * s->cfg.max_slots + sizeof(TaskD) * s->cfg.max_slots +
+  return 256 + 2 * sizeof(uint32_t) * s->cfg.max_slots + (sizeof(TaskD) * s->cfg.max_slots + 255) / 256 * 256 +
          sizeof(TileD) * kMaxIterTiles;
 }
 
@@ -312,14 +316,15 @@ int launch_iteration(ftv_server *s, Iter &it) {
   hdr[1] = s->cfg.max_slots;
   hdr[2] = nnew;
   hdr[3] = nfin;
-  // one copy per iteration: header, slot lists, new task records and tiles
-  const size_t bytes = tiles_off + sizeof(TileD) * ntiles;
-  HIPCHK(hipMemcpyAsync(it.d_buf, it.h_buf, bytes, hipMemcpyHostToDevice, s->stream));
+  // the slot-init kernel reads the table in place (pinned memory) and brings
+  // it into device memory for the vote and finalize kernels: no copy command
+  const size_t bytes = (tiles_off + sizeof(TileD) * ntiles + 7) / 8 * 8;
   const uint64_t *d_hdr = reinterpret_cast<const uint64_t *>(it.d_buf);
-  const uint32_t *d_slots = reinterpret_cast<const uint32_t *>(it.d_buf + 256);
   const uint32_t *d_fin = reinterpret_cast<const uint32_t *>(it.d_buf + 256 + slots_bytes);
-  const TaskD *d_new = reinterpret_cast<const TaskD *>(it.d_buf + 256 + 2 * slots_bytes);
-  HIPCHK(launch_slots_init(it.d_queue, s->d_acc, d_slots, d_hdr, d_new, s->d_tasks, s->stream));
+  const uint32_t *slots_h = reinterpret_cast<const uint32_t *>(it.h_buf_dev + 256);
+  const TaskD *new_h = reinterpret_cast<const TaskD *>(it.h_buf_dev + 256 + 2 * slots_bytes);
+  HIPCHK(launch_slots_init(it.d_queue, s->d_acc, it.h_buf_dev, it.d_buf, bytes, slots_h, new_h, nnew, s->d_tasks,
+                           s->stream));
   if (ntiles) {
     BatchLaunch b;
     b.tasks = s->d_tasks;
@@ -509,7 +514,8 @@ int ftv_server_create(const ftv_server_cfg *cfg, ftv_server **out) {
             hipHostGetDevicePointer((void **)&s->d_stats, s->h_stats, 0) == hipSuccess;
   for (auto &it : s->ring)
     ok = ok && hipEventCreateWithFlags(&it.ev, hipEventDisableTiming) == hipSuccess &&
-         hipHostMalloc(&it.h_buf, iter_bytes(s)) == hipSuccess &&
+         hipHostMalloc(&it.h_buf, iter_bytes(s), hipHostMallocMapped) == hipSuccess &&
+         hipHostGetDevicePointer((void **)&it.h_buf_dev, it.h_buf, 0) == hipSuccess && it.h_buf_dev &&
          hipMalloc(&it.d_buf, iter_bytes(s)) == hipSuccess && hipMalloc(&it.d_queue, 256) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();

@@ -49,9 +49,13 @@ __global__ __launch_bounds__(512) void k_vote_batch(BatchLaunch b) {
   const uint64_t ntiles = b.ntiles_dev[0];
   const uint64_t ntasks = b.ntiles_dev[1];
   uint64_t hint = 0;  // thread 0: task of the previous tile (tile numbers only grow)
+  bool first = true;  // a workgroup's first tile is its own index; the queue hands out the rest
   for (;;) {
     if (threadIdx.x == 0) {
-      const uint32_t q = __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t q = first ? blockIdx.x
+                               : gridDim.x + __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_AGENT);
+      first = false;
       s_tile = q;
       if (q < ntiles) {
         if (b.prefix) {
@@ -122,21 +126,34 @@ __global__ __launch_bounds__(64) void k_batch_finalize(BatchLaunch b) {
     finalize_task(b.tasks[i], b.acc + i * kNumCounters, false, s_tot);
 }
 
-// Serving iterations: re-arm the tile queue, and for the slots whose requests
-// join in this iteration (slots[0..hdr[2]) ) install their task records
-// (carried in the iteration's table) and clear their accumulators.
-__global__ __launch_bounds__(256) void k_slots_init(uint32_t *queue_head, uint64_t *acc,
-                                                    const uint32_t *slots, const uint64_t *hdr,
-                                                    const TaskD *newt, TaskD *tasks) {
+// Serving iterations: bring the iteration's table from pinned host memory into
+// device memory (the kernels after this one read it there), re-arm the tile
+// queue, and for the slots whose requests join in this iteration install
+// their task records and clear their accumulators -- both read straight from
+// the host table (slots[0..nnew), newt[0..nnew)).  No separate copy precedes
+// the kernel.
+// The host rewrites the table between iterations: it is read with
+// system-scope loads, coherent with the host's writes whatever the caches hold.
+__device__ __forceinline__ uint64_t ld_host64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t ld_host32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(256) void k_slots_init(uint32_t *queue_head, uint64_t *acc, const uint64_t *table_h,
+                                                    uint64_t *table_d, uint64_t table_words, const uint32_t *slots,
+                                                    const TaskD *newt, uint64_t nnew, TaskD *tasks) {
   static_assert(sizeof(TaskD) % 8 == 0, "task records are copied in 8-byte words");
   constexpr uint64_t W = sizeof(TaskD) / 8;
-  const uint64_t nnew = hdr[2];
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = gid; i < table_words; i += stride) table_d[i] = ld_host64(table_h + i);
   for (uint64_t i = gid; i < nnew * kNumCounters; i += stride)
-    acc[(uint64_t)slots[i / kNumCounters] * kNumCounters + i % kNumCounters] = 0;
+    acc[(uint64_t)ld_host32(slots + i / kNumCounters) * kNumCounters + i % kNumCounters] = 0;
   for (uint64_t i = gid; i < nnew * W; i += stride)
-    reinterpret_cast<uint64_t *>(tasks + slots[i / W])[i % W] = reinterpret_cast<const uint64_t *>(newt + i / W)[i % W];
+    reinterpret_cast<uint64_t *>(tasks + ld_host32(slots + i / W))[i % W] =
+        ld_host64(reinterpret_cast<const uint64_t *>(newt + i / W) + i % W);
   if (gid == 0) *queue_head = 0;
 }
 
@@ -179,9 +196,15 @@ hipError_t launch_batch_zero(const BatchLaunch &b, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const uint32_t *slots,
-                             const uint64_t *hdr, const TaskD *newt, TaskD *tasks, hipStream_t s) {
-  hipLaunchKernelGGL(k_slots_init, dim3(32), dim3(256), 0, s, queue_head, acc, slots, hdr, newt, tasks);
+hipError_t launch_slots_init(uint32_t *queue_head, uint64_t *acc, const void *table_h, void *table_d,
+                             uint64_t table_bytes, const uint32_t *slots_h, const TaskD *newt_h, uint64_t nnew,
+                             TaskD *tasks, hipStream_t s) {
+  const uint64_t words = (table_bytes + 7) / 8;
+  uint64_t grid = (words + 1023) / 1024;   // about four words per thread
+  grid = grid < 1 ? 1 : (grid > 256 ? 256 : grid);
+  hipLaunchKernelGGL(k_slots_init, dim3((uint32_t)grid), dim3(256), 0, s, queue_head, acc,
+                     static_cast<const uint64_t *>(table_h), static_cast<uint64_t *>(table_d), words, slots_h,
+                     newt_h, nnew, tasks);
   return hipGetLastError();
 }
 
