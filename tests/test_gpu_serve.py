@@ -156,3 +156,56 @@ def test_budget_queue_and_errors(gpu):
         srv.submit_vote([xi, xi, xi], gpu.ulp(1))
     assert e.value.code == gpu.E_DTYPE
     srv.close()
+
+
+def test_concurrent_submitters(gpu):
+    """Submit, poll and release are thread-safe: four host threads serve their
+    own requests at once (some with server-owned outputs), and every result
+    equals the oracle's."""
+    import threading
+    import torch
+    rng = np.random.default_rng(77)
+    reqs = _requests(gpu, rng, 32, 200000)
+    torch.cuda.synchronize()
+    refs = [oracle.vote(r["reps"], r["tol_o"]) for r in reqs]
+    srv = gpu.Server(hbm_budget_bytes=8 << 30, arena_bytes=512 << 20, chunk_bytes=512 << 10, max_slots=16)
+    results = [None] * len(reqs)
+    errors = []
+
+    def worker(w):
+        try:
+            for i in range(w, len(reqs), 4):
+                r = reqs[i]
+                own = i % 3 == 0   # server-owned outputs for every third request
+                c, m = (None, None) if own else r["outs"][0]
+                tk = srv.submit_vote(r["t"], r["tol_f"], c, m, n=r["n"])
+                res = srv.poll(tk, -1)
+                n = r["n"]
+                u = U[r["reps"][0].dtype]
+                if own:
+                    cons = _d2h(res.consensus, n * r["reps"][0].itemsize, u) if n else np.zeros(0, u)
+                    mask = _d2h(res.mask, n, np.uint8) if n else np.zeros(0, np.uint8)
+                else:
+                    cons = c[:n].cpu().numpy().view(u)
+                    mask = m[:n].cpu().numpy()
+                results[i] = (res.status, cons, mask, gpu.result_stats(res))
+                srv.release(tk)
+        except Exception as e:  # reported by the main thread
+            errors.append(repr(e))
+
+    print("case: four threads submitting 32 requests", flush=True)
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=60)
+    srv.close()
+    assert not errors, errors
+    for i, (r, ref) in enumerate(zip(reqs, refs)):
+        status, cons, mask, s = results[i]
+        u = U[r["reps"][0].dtype]
+        k = r["k"]
+        assert status == 0, i
+        assert np.array_equal(cons, ref.consensus.view(u)) and np.array_equal(mask, ref.mask), i
+        assert np.array_equal(s["pair"][:k, :k], ref.pair) and s["no_majority"] == ref.no_majority, i
+        assert (s["verdict"], s["winner"]) == (ref.verdict, ref.winner), i
