@@ -31,7 +31,8 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote_task.hpp", "paper_1405_2912_amd/csrc/ftv_vote_f32.hip",
                   "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
 BATCH_SOURCES = ["paper_1405_2912_amd/csrc/ftv_vote_batch.hip", "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
-BLOCK_SOURCES = ["paper_1405_2912_amd/csrc/ftv_blocks.hip", "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
+BLOCK_SOURCES = ["paper_1405_2912_amd/csrc/ftv_hash.hip", "paper_1405_2912_amd/csrc/ftv_blocks.hip",
+                 "paper_1405_2912_amd/csrc/ftv_blocks_dev.hpp", "paper_1405_2912_amd/csrc/ftv_vote_dev.hpp"]
 
 
 def log(*a):

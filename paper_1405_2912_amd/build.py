@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libftv.so")
 
 SOURCES = ["ftv_vote_f32.hip", "ftv_vote_f64.hip", "ftv_vote_i32.hip", "ftv_vote_i64.hip", "ftv_vote_batch.hip",
            "ftv_vote_noalloc.hip",
-           "ftv_blocks.hip", "ftv_copy.hip", "ftv_api.cpp", "ftv_server.cpp", "ftv_units.cpp", "ftv_mm.cpp",
+           "ftv_hash.hip", "ftv_blocks.hip", "ftv_copy.hip", "ftv_api.cpp", "ftv_server.cpp", "ftv_units.cpp", "ftv_mm.cpp",
            "ftv_run.cpp", "ftv_host.cpp", "ftv_place.cpp"]
 
 ARCH = "gfx950"

@@ -130,6 +130,10 @@ struct BlockVoteD {
   uint64_t *acc;          // device workspace [16], left zeroed by the finalize kernel
 };
 hipError_t launch_vote_blocks(const BlockVoteD &b, int num_cus, hipStream_t s);
+// Pass 1 of the block vote: whole-block fingerprints of every replica (replica
+// 0 also streamed into the consensus, its mask bytes zeroed) and the vote of
+// the partial last block.
+hipError_t launch_blocks_hash(const BlockVoteD &b, hipStream_t s);
 
 // ---- sibling manager helpers (ftv_copy.hip) ------------------------------
 // Device-to-device copy of `bytes` (both pointers 16-byte aligned).
