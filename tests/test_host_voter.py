@@ -130,6 +130,25 @@ def test_host_voter_planted_nonzero_argmin_winner(ftv, dtype):
                 _check(ftv.vote_host(reps, tol_f, threads=threads), ref, len(per), f"{dtype} {per} {nomaj}")
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_host_voter_tolerance_edges(ftv, dtype):
+    """Elements on the tolerance edges (ULP steps around m across zero,
+    denormals, max, inf and the NaN keys; relative distances at the delta;
+    ties; a random strict majority per element), one thread and several."""
+    from edge_sets import boundary_set
+    rng = np.random.default_rng(91 + np.dtype(dtype).itemsize)
+    tiny = float(np.finfo(dtype).smallest_normal) * 4
+    for k in (2, 3, 4, 5, 7):
+        for m, delta, anchored in ((1, 1e-3, False), (1000, 1e-6, False), (4, 1e-3, True)):
+            reps = boundary_set(rng, dtype, k, 20011, m, delta, anchored)
+            for tol_o, tol_f in ((oracle.ulp(m), ftv.ulp(m)), (oracle.exact(), ftv.exact()),
+                                 (oracle.rel(delta), ftv.rel(delta)), (oracle.rel(delta, tiny), ftv.rel(delta, tiny))):
+                ref = oracle.vote(reps, tol_o)
+                for threads in (1, 3):
+                    _check(ftv.vote_host(reps, tol_f, threads=threads), ref, k,
+                           f"{np.dtype(dtype).name} k={k} m={m} anchored={anchored} tol={tol_o} threads={threads}")
+
+
 def test_host_voter_large_many_threads(ftv):
     """The single-large-task recipe at 2^22 elements on every core: counts are
     per thread and summed, so the result equals the sequential oracle's."""
