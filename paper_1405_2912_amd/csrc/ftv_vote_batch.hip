@@ -52,11 +52,15 @@ __global__ __launch_bounds__(512) void k_vote_batch(BatchLaunch b) {
   const uint64_t ntasks = b.ntiles_dev[1];
   uint64_t hint = 0;  // thread 0: task of the previous tile (tile numbers only grow)
   bool first = true;  // a workgroup's first tile is its own index; the queue hands out the rest
+  // when the grid covers every tile, each tile is some workgroup's first and
+  // the queue has nothing to hand out: no atomic round trip before exiting
+  const bool queue = gridDim.x < ntiles;
   for (;;) {
     if (threadIdx.x == 0) {
       const uint32_t q = first ? blockIdx.x
-                               : gridDim.x + __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED,
-                                                                    __HIP_MEMORY_SCOPE_AGENT);
+                         : !queue ? (uint32_t)ntiles
+                                  : gridDim.x + __hip_atomic_fetch_add(b.queue_head, 1u, __ATOMIC_RELAXED,
+                                                                       __HIP_MEMORY_SCOPE_AGENT);
       first = false;
       s_tile = q;
       if (q < ntiles) {
