@@ -10,9 +10,11 @@
 // Layout of the hot loop: every lane streams one 16-byte vector of each of the
 // k replicas per step (global_load_dwordx4, non-temporal), votes the 4 (fp32,
 // i32) or 2 (fp64, i64) elements in registers, and writes one 16-byte
-// consensus vector and 4 or 2 mask bytes.  Mismatch counting is done per wave
-// with ballots into wave-uniform (scalar) accumulators, and only for vectors
-// where some lane saw a disagreement, which is rare.
+// consensus vector and 4 or 2 mask bytes.  Mismatch counting is done only in
+// waves where some lane saw a disagreement: into per-lane counters folded once
+// per workgroup (the per-task kernel) or with ballots into wave-uniform
+// (scalar) accumulators (the batched and block kernels, where registers are
+// scarcer and disagreements rare).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -352,6 +354,19 @@ __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_general_dyn(
   return o;
 }
 
+// k = 3 with three differing bit patterns: the three tolerance tests and the
+// case analysis.
+template <int DT, int TOL>
+__device__ __forceinline__ ElemOut<typename VT<DT>::W> vote3_slow(const typename VT<DT>::W (&x)[3],
+                                                                  const TolD &t) {
+  ElemOut<typename VT<DT>::W> o;
+  const uint32_t ne = (uint32_t)!eqv<DT, TOL>(x[0], x[1], t) | ((uint32_t)!eqv<DT, TOL>(x[0], x[2], t) << 1) |
+                      ((uint32_t)!eqv<DT, TOL>(x[1], x[2], t) << 2);
+  o.ne = ne;
+  o.cons = vote3_general<DT>(x, ne, o.mb);
+  return o;
+}
+
 // Elements with two or more differing bit patterns (k >= 3).
 template <int DT, int TOL, int K>
 __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_slow(const typename VT<DT>::W (&x)[K],
@@ -359,13 +374,7 @@ __device__ __forceinline__ ElemOut<typename VT<DT>::W> vote_slow(const typename 
                                                                  const void *const (&rep)[FTV_MAX_K],
                                                                  uint64_t i) {
   if constexpr (K == 3) {
-    ElemOut<typename VT<DT>::W> o;
-    const uint32_t ne = (uint32_t)!eqv<DT, TOL>(x[0], x[1], t) |
-                        ((uint32_t)!eqv<DT, TOL>(x[0], x[2], t) << 1) |
-                        ((uint32_t)!eqv<DT, TOL>(x[1], x[2], t) << 2);
-    o.ne = ne;
-    o.cons = vote3_general<DT>(x, ne, o.mb);
-    return o;
+    return vote3_slow<DT, TOL>(x, t);
   } else {
     return vote_general_dyn<DT, TOL>(rep, K, i, t);
   }
@@ -393,6 +402,7 @@ template <int K>
 struct Acc {
   static constexpr int NP = NPair<K>::value;
   static constexpr int NC = NP + K + 1;
+  static constexpr bool kLane = false;
   uint64_t c[NC];
   __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -406,6 +416,50 @@ struct Acc {
 #pragma unroll
     for (int r = 0; r < K; ++r) c[NP + r] += __popcll(__ballot(valid && ((mb >> r) & 1u)));
     c[NP + K] += __popcll(__ballot(valid && (mb & 0x80u)));
+  }
+};
+
+// The same counts with a per-lane stage: in a wave where some lane saw a
+// mismatch, each counter takes one 32-bit add per lane (no ballot, no scalar
+// dependency chain), and fold() sums the lanes into the wave-uniform 64-bit
+// counters once, before the workgroup total.  Waves without a mismatch skip
+// the adds as in Acc.  When most elements disagree (a corrupted replica, or
+// float replicas under EXACT) the ballot chain of Acc, with one wave per SIMD,
+// is what limits the kernel.  A lane's 32-bit counters hold at most the
+// elements that lane votes between folds.
+template <int K>
+struct LaneAcc {
+  static constexpr int NP = NPair<K>::value;
+  static constexpr int NC = NP + K + 1;
+  static constexpr bool kLane = true;
+  uint64_t c[NC];
+  uint32_t l[NC];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      c[i] = 0;
+      l[i] = 0;
+    }
+  }
+  __device__ __forceinline__ void add(bool valid, uint32_t ne, uint32_t mb) {
+    if (__ballot(valid && ne != 0u) == 0ull) return;  // wave-uniform
+    const uint32_t e = valid ? ne : 0u, m = valid ? mb : 0u;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) l[q] += (e >> q) & 1u;
+#pragma unroll
+    for (int r = 0; r < K; ++r) l[NP + r] += (m >> r) & 1u;
+    l[NP + K] += (m >> 7) & 1u;
+  }
+  // Called by every lane of the wave.
+  __device__ __forceinline__ void fold() {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      uint32_t v = l[i];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      c[i] += v;
+      l[i] = 0;
+    }
   }
 };
 
@@ -483,13 +537,59 @@ __device__ __forceinline__ void stream_store8(uintptr_t base, uint32_t off, uint
   __builtin_amdgcn_raw_buffer_store_b64(w, stream_rsrc(base), off, 0, kStreamStorePolicy);
 }
 
+// The votes of the V elements of one vector (x[r][e]: element e of replica
+// r).  k = 2: one tolerance test each.  k >= 3: the at-most-one-outlier form;
+// the elements with more differing patterns are then voted in place from the
+// registers (one wave-uniform branch per vector, taken only when some lane
+// has such an element) for k = 3, and for k >= 4 when INL; otherwise they are
+// returned as bits for the fix-up pass, which reloads each element and keeps
+// the general vote out of the streaming registers (the batched kernel, whose
+// register budget is that of its largest specialization).  With one replica
+// corrupted and rounding noise between the others most elements have three
+// patterns: the fix-up pass then took 3.7 ms for the k = 3 fp32 16384^2 task
+// against 0.77 ms for the clean one, the in-place vote 1.65 ms.
+template <int DT, int TOL, int K, int V, bool INL>
+__device__ __forceinline__ uint32_t vote_vec(const typename VT<DT>::W (&x)[K][V], const TolD &tol, bool valid,
+                                             ElemOut<typename VT<DT>::W> (&o)[V]) {
+  using W = typename VT<DT>::W;
+  uint32_t gen = 0;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    W xe[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) xe[r] = x[r][e];
+    if constexpr (K == 2) {
+      o[e] = vote_general<DT, TOL, 2>(xe, tol);
+    } else {
+      bool g = false;
+      o[e] = vote_fast<DT, TOL, K>(xe, tol, g);
+      gen |= (uint32_t)(g && valid) << e;
+    }
+  }
+  if constexpr (K == 3 || (K >= 4 && INL)) {
+    if (__ballot(gen != 0u) != 0ull) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if ((gen >> e) & 1u) {
+          W xe[K];
+#pragma unroll
+          for (int r = 0; r < K; ++r) xe[r] = x[r][e];
+          if constexpr (K == 3) o[e] = vote3_slow<DT, TOL>(xe, tol);
+          else o[e] = vote_general<DT, TOL, K>(xe, tol);
+        }
+      }
+    }
+    gen = 0;
+  }
+  return gen;
+}
+
 // Vote vectors [v0, v1) of a task with the calling workgroup (vector path:
 // vector = 16 bytes; scalar path: vector = one element).  Lane `tid` handles
 // v0 + tid + u*nthreads for u < U in each step, all loads of a step issued
 // before any vote.
-template <int DT, int TOL, int K, bool VEC, int U>
-__device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t v1, Acc<K> &acc,
-                                           bool nt) {
+template <int DT, int TOL, int K, bool VEC, int U, bool INL = false, class A>
+__device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t v1, A &acc, bool nt) {
   using W = typename VT<DT>::W;
   constexpr int V = VEC ? Vec<W>::V : 1;
   const uint32_t nth = blockDim.x;
@@ -537,20 +637,14 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
       const bool valid = vi < v1;
       W cv[V];
       uint32_t mbs = 0;
+      ElemOut<W> o[V];
+      const uint32_t gen = vote_vec<DT, TOL, K, V, INL>(x[u], t.tol, valid, o);
+      need |= gen << (u * V);
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        W xe[K];
-#pragma unroll
-        for (int r = 0; r < K; ++r) xe[r] = x[u][r][e];
-        bool general = false;
-        ElemOut<W> o;
-        if constexpr (K == 2) o = vote_general<DT, TOL, 2>(xe, t.tol);
-        else o = vote_fast<DT, TOL, K>(xe, t.tol, general);
-        general = general && valid;
-        need |= (uint32_t)general << (u * V + e);
-        cv[e] = o.cons;
-        mbs |= o.mb << (8 * e);
-        acc.add(valid && !general, o.ne, o.mb);
+        cv[e] = o[e].cons;
+        mbs |= o[e].mb << (8 * e);
+        acc.add(valid && !((gen >> e) & 1u), o[e].ne, o[e].mb);
       }
       if (valid) {
         if constexpr (VEC) {
@@ -574,11 +668,11 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
         }
       }
     }
-    // fix-up pass (rare): the loaded vectors are dead here, so the general
-    // vote does not add to the register footprint of the fast pass.  The
-    // element is reloaded, voted and stored again after this lane's earlier
-    // stores have completed.
-    if constexpr (K >= 3) {
+    // fix-up pass (k >= 4 without INL): the loaded vectors are dead here, so
+    // the general vote does not add to the register footprint of the fast
+    // pass.  The element is reloaded, voted and stored again after this lane's
+    // earlier stores have completed.
+    if constexpr (K >= 4 && !INL) {
       if (__ballot(need != 0u) != 0ull) {
         __threadfence_block();
 #pragma unroll 1
@@ -606,8 +700,8 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
 // against resources based at the step; a NULL output gets a resource of size
 // zero, whose stores the hardware discards, so the step has no branch on the
 // optional outputs and the loads, votes and stores form one straight block.
-template <int DT, int TOL, int K, int U>
-__device__ __forceinline__ void vote_step_full(const TaskD &t, uint64_t base, Acc<K> &acc) {
+template <int DT, int TOL, int K, int U, bool INL = false, class A>
+__device__ __forceinline__ void vote_step_full(const TaskD &t, uint64_t base, A &acc) {
   using W = typename VT<DT>::W;
   constexpr int V = Vec<W>::V;
   const uint32_t nth = blockDim.x;
@@ -630,27 +724,22 @@ __device__ __forceinline__ void vote_step_full(const TaskD &t, uint64_t base, Ac
   for (int u = 0; u < U; ++u) {
     W cv[V];
     uint32_t mbs = 0;
+    ElemOut<W> o[V];
+    const uint32_t gen = vote_vec<DT, TOL, K, V, INL>(x[u], t.tol, true, o);
+    need |= gen << (u * V);
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      W xe[K];
-#pragma unroll
-      for (int r = 0; r < K; ++r) xe[r] = x[u][r][e];
-      bool general = false;
-      ElemOut<W> o;
-      if constexpr (K == 2) o = vote_general<DT, TOL, 2>(xe, t.tol);
-      else o = vote_fast<DT, TOL, K>(xe, t.tol, general);
-      need |= (uint32_t)general << (u * V + e);
-      cv[e] = o.cons;
-      mbs |= o.mb << (8 * e);
-      acc.add(!general, o.ne, o.mb);
+      cv[e] = o[e].cons;
+      mbs |= o[e].mb << (8 * e);
+      acc.add(!((gen >> e) & 1u), o[e].ne, o[e].mb);
     }
     const uint32_t so = (uint32_t)u * nth + tid;
     __builtin_amdgcn_raw_buffer_store_b128(Vec<W>::pack(cv), rc, so * 16u, 0, kStreamStorePolicy);
     if constexpr (V == 4) __builtin_amdgcn_raw_buffer_store_b32(mbs, rm, so * 4u, 0, kStreamStorePolicy);
     else __builtin_amdgcn_raw_buffer_store_b16((uint16_t)mbs, rm, so * 2u, 0, kStreamStorePolicy);
   }
-  // fix-up pass (rare), as in vote_range
-  if constexpr (K >= 3) {
+  // fix-up pass (k >= 4 without INL), as in vote_range
+  if constexpr (K >= 4 && !INL) {
     if (__ballot(need != 0u) != 0ull) {
       __threadfence_block();
 #pragma unroll 1
@@ -673,8 +762,8 @@ __device__ __forceinline__ void vote_step_full(const TaskD &t, uint64_t base, Ac
 }
 
 // Elements [nvec*V, n) of a vector-path task (fewer than V), one per lane.
-template <int DT, int TOL, int K>
-__device__ __forceinline__ void vote_tail(const TaskD &t, Acc<K> &acc) {
+template <int DT, int TOL, int K, class A>
+__device__ __forceinline__ void vote_tail(const TaskD &t, A &acc) {
   using W = typename VT<DT>::W;
   constexpr int V = Vec<W>::V;
   const uint64_t i = t.nvec * V + threadIdx.x;
@@ -692,9 +781,10 @@ __device__ __forceinline__ void vote_tail(const TaskD &t, Acc<K> &acc) {
 
 // Sum the wave accumulators of a workgroup; the result for counter q is
 // returned in thread q (q < NC) of the workgroup.  `sh` holds >= 16*32 u64.
-template <int K>
-__device__ __forceinline__ uint64_t block_total(const Acc<K> &acc, uint64_t *sh) {
-  constexpr int NC = Acc<K>::NC;
+template <int K, class A>
+__device__ __forceinline__ uint64_t block_total(A &acc, uint64_t *sh) {
+  constexpr int NC = A::NC;
+  if constexpr (A::kLane) acc.fold();
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
   if (lane == 0) {

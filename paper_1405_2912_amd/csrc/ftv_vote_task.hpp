@@ -3,7 +3,10 @@
 //
 // A grid-stride loop over tiles of 16-byte vectors; each workgroup reduces its
 // wave accumulators and adds the non-zero totals to the launch's device
-// accumulators (most workgroups see no disagreement and add nothing).  A
+// accumulators (most workgroups see no disagreement and add nothing).  The
+// kernel runs one workgroup per CU, so registers are plentiful: counts go to
+// per-lane counters and the general vote of an element with several differing
+// values runs in place from the loaded registers.  A
 // one-workgroup finalize kernel on the same stream then decides the verdict,
 // writes the stats record and clears the accumulators: the kernel boundary
 // orders the counts before the verdict, so the vote kernel needs neither a
@@ -79,20 +82,20 @@ __global__ __launch_bounds__((TaskShape<DT, TOL, K, VEC>::threads)) void k_vote_
   __shared__ uint64_t sh[16 * kNumCounters];
   using S = TaskShape<DT, TOL, K, VEC>;
   constexpr int U = S::U;
-  constexpr int NC = Acc<K>::NC;
-  Acc<K> acc;
+  constexpr int NC = LaneAcc<K>::NC;
+  LaneAcc<K> acc;
   acc.zero();
   const uint64_t tile = (uint64_t)blockDim.x * U;
   if constexpr (S::lean) {
     // full tiles grid-stride, then the partial tile (if any) by its owner
     const uint64_t nfull = t.nvec / tile;
-    for (uint64_t i = blockIdx.x; i < nfull; i += gridDim.x) vote_step_full<DT, TOL, K, U>(t, i * tile, acc);
+    for (uint64_t i = blockIdx.x; i < nfull; i += gridDim.x) vote_step_full<DT, TOL, K, U, true>(t, i * tile, acc);
     if (nfull * tile < t.nvec && blockIdx.x == nfull % gridDim.x)
-      vote_range<DT, TOL, K, VEC, U>(t, nfull * tile, t.nvec, acc, true);
+      vote_range<DT, TOL, K, VEC, U, true>(t, nfull * tile, t.nvec, acc, true);
   } else {
     for (uint64_t b = (uint64_t)blockIdx.x * tile; b < t.nvec; b += (uint64_t)gridDim.x * tile) {
       const uint64_t e = b + tile < t.nvec ? b + tile : t.nvec;
-      vote_range<DT, TOL, K, VEC, U>(t, b, e, acc, true);
+      vote_range<DT, TOL, K, VEC, U, true>(t, b, e, acc, true);
     }
   }
   if constexpr (VEC) {
