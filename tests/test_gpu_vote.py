@@ -298,3 +298,58 @@ def test_two_streams_share_a_context(gpu, ctx):
             assert np.array_equal(s["pair"][:3, :3], ref.pair), (j, i)
             assert np.array_equal(s["disagree"][:3], ref.disagree), (j, i)
             assert s["no_majority"] == ref.no_majority and (s["verdict"], s["winner"]) == (ref.verdict, ref.winner)
+
+
+def _corrupted_set(rng, dtype, k, n):
+    """k replicas: a base, rounding noise (+-1..3 ULP on 30% of the elements)
+    on replica 1, replica 2 replaced by unrelated values; the rest copies of
+    the base or of replica 1.  Most elements then hold three different bit
+    patterns, the case the in-place general vote and the fix-up pass decide."""
+    dtype = np.dtype(dtype)
+    base = rng.standard_normal(n).astype(dtype)
+    noisy = base.copy()
+    synth.ulp_noise(noisy, 4321, 1, round(0.3 * (1 << 24)), 3)
+    garbage = (rng.standard_normal(n) * 1e3).astype(dtype)
+    reps = [base, noisy, garbage]
+    for r in range(3, k):
+        reps.append((base if r % 2 else noisy).copy())
+    return reps[:k]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_corrupted_replica_with_rounding_noise(gpu, ctx, dtype):
+    """Per-task launches (general vote in place) and one batched launch
+    (k >= 4 through the fix-up pass) against the oracle, k = 3..7."""
+    import ctypes
+    import torch
+    rng = np.random.default_rng(515 + np.dtype(dtype).itemsize)
+    dev = torch.device("cuda:0")
+    tasks = []
+    for k in (3, 4, 5, 6, 7):
+        reps = _corrupted_set(rng, dtype, k, 100003)
+        for tol_o, tol_f in ((oracle.ulp(4), gpu.ulp(4)), (oracle.exact(), gpu.exact()),
+                             (oracle.rel(1e-3), gpu.rel(1e-3))):
+            where = f"corrupted {np.dtype(dtype).name} k={k} tol={tol_o}"
+            print("case:", where, flush=True)
+            ref = oracle.vote(reps, tol_o)
+            _check(_run(gpu, ctx, reps, tol_f), ref, k, where)
+            tasks.append((where, reps, tol_o, tol_f, ref))
+    # the same tasks in one batched launch
+    outs = []
+    stats = gpu.stats_tensor(dev, len(tasks))
+    descs = []
+    for i, (where, reps, tol_o, tol_f, ref) in enumerate(tasks):
+        t = [torch.from_numpy(r).to(dev) for r in reps]
+        cons = torch.empty(reps[0].size, dtype=t[0].dtype, device=dev)
+        mask = torch.empty(reps[0].size, dtype=torch.uint8, device=dev)
+        d = gpu.make_desc(t, tol_f, cons, mask, None)
+        d.stats = stats.data_ptr() + i * ctypes.sizeof(gpu.Stats)
+        descs.append(d)
+        outs.append((t, cons, mask))
+    print(f"case: one batch of {len(descs)} corrupted-replica tasks", flush=True)
+    gpu.vote_batch(ctx, descs)
+    torch.cuda.synchronize()
+    for i, (where, reps, tol_o, tol_f, ref) in enumerate(tasks):
+        _, cons, mask = outs[i]
+        _check((cons.cpu().numpy(), mask.cpu().numpy(), gpu.read_stats(stats, i)), ref, len(reps),
+               "batched " + where)
