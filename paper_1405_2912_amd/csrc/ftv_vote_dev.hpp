@@ -450,8 +450,14 @@ struct LaneAcc {
     for (int r = 0; r < K; ++r) l[NP + r] += (m >> r) & 1u;
     l[NP + K] += (m >> 7) & 1u;
   }
-  // Called by every lane of the wave.
+  // Called by every lane of the wave.  A wave that counted nothing (most
+  // waves of a clean task) skips the reductions: they are a chain of
+  // cross-lane steps that a short kernel would otherwise wait for.
   __device__ __forceinline__ void fold() {
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) any |= l[i];
+    if (__ballot(any != 0u) == 0ull) return;  // wave-uniform
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
       uint32_t v = l[i];
@@ -567,7 +573,9 @@ __device__ __forceinline__ uint32_t vote_vec(const typename VT<DT>::W (&x)[K][V]
     }
   }
   if constexpr (K == 3 || (K >= 4 && INL)) {
-    if (__ballot(gen != 0u) != 0ull) {
+    // marked unlikely so that the general votes are laid out after the
+    // streaming path instead of inside it
+    if (__builtin_expect(__ballot(gen != 0u) != 0ull, 0)) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         if ((gen >> e) & 1u) {
