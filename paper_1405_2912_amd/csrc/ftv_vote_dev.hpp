@@ -645,14 +645,34 @@ __device__ __forceinline__ void vote_range(const TaskD &t, uint64_t v0, uint64_t
       const bool valid = vi < v1;
       W cv[V];
       uint32_t mbs = 0;
-      ElemOut<W> o[V];
-      const uint32_t gen = vote_vec<DT, TOL, K, V, INL>(x[u], t.tol, valid, o);
-      need |= gen << (u * V);
+      if constexpr (K == 3 || INL) {
+        ElemOut<W> o[V];
+        const uint32_t gen = vote_vec<DT, TOL, K, V, INL>(x[u], t.tol, valid, o);
+        need |= gen << (u * V);
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        cv[e] = o[e].cons;
-        mbs |= o[e].mb << (8 * e);
-        acc.add(valid && !((gen >> e) & 1u), o[e].ne, o[e].mb);
+        for (int e = 0; e < V; ++e) {
+          cv[e] = o[e].cons;
+          mbs |= o[e].mb << (8 * e);
+          acc.add(valid && !((gen >> e) & 1u), o[e].ne, o[e].mb);
+        }
+      } else {
+        // element by element, each counted right after its vote (this order
+        // keeps the scalar registers of the ballot counts of large k unspilled)
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          W xe[K];
+#pragma unroll
+          for (int r = 0; r < K; ++r) xe[r] = x[u][r][e];
+          bool general = false;
+          ElemOut<W> o;
+          if constexpr (K == 2) o = vote_general<DT, TOL, 2>(xe, t.tol);
+          else o = vote_fast<DT, TOL, K>(xe, t.tol, general);
+          general = general && valid;
+          need |= (uint32_t)general << (u * V + e);
+          cv[e] = o.cons;
+          mbs |= o.mb << (8 * e);
+          acc.add(valid && !general, o.ne, o.mb);
+        }
       }
       if (valid) {
         if constexpr (VEC) {
@@ -732,14 +752,32 @@ __device__ __forceinline__ void vote_step_full(const TaskD &t, uint64_t base, A 
   for (int u = 0; u < U; ++u) {
     W cv[V];
     uint32_t mbs = 0;
-    ElemOut<W> o[V];
-    const uint32_t gen = vote_vec<DT, TOL, K, V, INL>(x[u], t.tol, true, o);
-    need |= gen << (u * V);
+    if constexpr (K == 3 || INL) {
+      ElemOut<W> o[V];
+      const uint32_t gen = vote_vec<DT, TOL, K, V, INL>(x[u], t.tol, true, o);
+      need |= gen << (u * V);
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      cv[e] = o[e].cons;
-      mbs |= o[e].mb << (8 * e);
-      acc.add(!((gen >> e) & 1u), o[e].ne, o[e].mb);
+      for (int e = 0; e < V; ++e) {
+        cv[e] = o[e].cons;
+        mbs |= o[e].mb << (8 * e);
+        acc.add(!((gen >> e) & 1u), o[e].ne, o[e].mb);
+      }
+    } else {
+      // element by element, as in vote_range
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        W xe[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) xe[r] = x[u][r][e];
+        bool general = false;
+        ElemOut<W> o;
+        if constexpr (K == 2) o = vote_general<DT, TOL, 2>(xe, t.tol);
+        else o = vote_fast<DT, TOL, K>(xe, t.tol, general);
+        need |= (uint32_t)general << (u * V + e);
+        cv[e] = o.cons;
+        mbs |= o.mb << (8 * e);
+        acc.add(!general, o.ne, o.mb);
+      }
     }
     const uint32_t so = (uint32_t)u * nth + tid;
     __builtin_amdgcn_raw_buffer_store_b128(Vec<W>::pack(cv), rc, so * 16u, 0, kStreamStorePolicy);

@@ -4,9 +4,9 @@
 // A grid-stride loop over tiles of 16-byte vectors; each workgroup reduces its
 // wave accumulators and adds the non-zero totals to the launch's device
 // accumulators (most workgroups see no disagreement and add nothing).  The
-// kernel runs one workgroup per CU, so registers are plentiful: counts go to
-// per-lane counters and the general vote of an element with several differing
-// values runs in place from the loaded registers.  A
+// kernel runs one workgroup per CU, so registers are plentiful: up to k = 5
+// counts go to per-lane counters and the general vote of an element with
+// several differing values runs in place from the loaded registers.  A
 // one-workgroup finalize kernel on the same stream then decides the verdict,
 // writes the stats record and clears the accumulators: the kernel boundary
 // orders the counts before the verdict, so the vote kernel needs neither a
@@ -17,6 +17,8 @@
 // loaded from one code object holding every vote kernel (about 1 MB of code)
 // than from a small one.
 #pragma once
+
+#include <type_traits>
 
 #include "ftv_internal.hpp"
 #include "ftv_vote_dev.hpp"
@@ -77,25 +79,40 @@ struct TaskShape {
   static constexpr bool lean = s.lean;
 };
 
+// In-place general votes and per-lane counts up to k = 5.  From k = 6 on the
+// tolerance tests of an in-place general vote (15 or 21 lane masks) and the
+// counts overflow the scalar registers, which the compiler then spills
+// through lanes of a vector register: for the fp32 16384^2 task the kernel
+// measured 1.86 ms at k = 7 that way against 1.64-1.67 ms with the
+// element-by-element loop, ballot counts and the fix-up pass, and 1.48 ms
+// against 1.45 ms at k = 6, so k = 6 and 7 keep that loop.
+template <int K>
+struct TaskAcc {
+  static constexpr bool inl = K <= 5;
+  using type = typename std::conditional<(K <= 5), LaneAcc<K>, Acc<K>>::type;
+};
+
 template <int DT, int TOL, int K, bool VEC>
 __global__ __launch_bounds__((TaskShape<DT, TOL, K, VEC>::threads)) void k_vote_task(TaskD t, VoteWs ws) {
   __shared__ uint64_t sh[16 * kNumCounters];
   using S = TaskShape<DT, TOL, K, VEC>;
   constexpr int U = S::U;
-  constexpr int NC = LaneAcc<K>::NC;
-  LaneAcc<K> acc;
+  constexpr bool INL = TaskAcc<K>::inl;
+  using A = typename TaskAcc<K>::type;
+  constexpr int NC = A::NC;
+  A acc;
   acc.zero();
   const uint64_t tile = (uint64_t)blockDim.x * U;
   if constexpr (S::lean) {
     // full tiles grid-stride, then the partial tile (if any) by its owner
     const uint64_t nfull = t.nvec / tile;
-    for (uint64_t i = blockIdx.x; i < nfull; i += gridDim.x) vote_step_full<DT, TOL, K, U, true>(t, i * tile, acc);
+    for (uint64_t i = blockIdx.x; i < nfull; i += gridDim.x) vote_step_full<DT, TOL, K, U, INL>(t, i * tile, acc);
     if (nfull * tile < t.nvec && blockIdx.x == nfull % gridDim.x)
-      vote_range<DT, TOL, K, VEC, U, true>(t, nfull * tile, t.nvec, acc, true);
+      vote_range<DT, TOL, K, VEC, U, INL>(t, nfull * tile, t.nvec, acc, true);
   } else {
     for (uint64_t b = (uint64_t)blockIdx.x * tile; b < t.nvec; b += (uint64_t)gridDim.x * tile) {
       const uint64_t e = b + tile < t.nvec ? b + tile : t.nvec;
-      vote_range<DT, TOL, K, VEC, U, true>(t, b, e, acc, true);
+      vote_range<DT, TOL, K, VEC, U, INL>(t, b, e, acc, true);
     }
   }
   if constexpr (VEC) {
