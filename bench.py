@@ -591,6 +591,18 @@ def bench_mixed(ftv, ctx, side=16384, reps_timed=3, chunk_mib=64):
     return out
 
 
+def fastest_unit(times):
+    """The fastest of (name, microseconds) pairs listed from the simplest unit
+    (one host thread) to the most involved (the GPU): a later unit counts as
+    faster only when it takes at most 90% of the time of the current pick, so
+    ties within timing noise go to the simpler unit."""
+    best_name, best = times[0]
+    for name, us in times[1:]:
+        if us <= 0.9 * best:
+            best_name, best = name, us
+    return best_name
+
+
 def bench_placement(ftv, ctx, runs=5):
     """Voter units by data size (the paper's Fig. 3 analogue): k=3 fp32 replicas
     of 1 KiB .. 64 MiB each, in host memory and in device memory, voted by one
@@ -629,7 +641,7 @@ def bench_placement(ftv, ctx, runs=5):
                 row[names[u] + "_us"] = round(ts[len(ts) // 2] * 1e6, 1)
                 results.append((cons.cpu() if cons.is_cuda else cons).numpy().view("u4").copy())
             row["identical"] = all((x == results[0]).all() for x in results[1:])
-            row["fastest"] = min((row[names[u] + "_us"], names[u]) for u in units)[1]
+            row["fastest"] = fastest_unit([(names[u], row[names[u] + "_us"]) for u in units])
             # the placement left to itself: what it settles on after trying every unit
             db = ftv.VoterDB(check_interval=0, host_threads=0)
             chosen = []
@@ -653,7 +665,7 @@ def bench_placement(ftv, ctx, runs=5):
         d = next(r for r in rows if r["data"] == "device" and r["bytes_per_replica"] == nbytes)
         t = {"host_1_thread": h["host_1_thread_us"], "host_all_cores": h["host_all_cores_us"], "gpu": d["gpu_us"]}
         own.append({"bytes_per_replica": nbytes, **{k + "_us": v for k, v in t.items()},
-                    "fastest": min((v, k) for k, v in t.items())[1]})
+                    "fastest": fastest_unit(list(t.items()))})
     cross["data_in_each_units_memory"] = {
         "rows": own,
         "all_cores_fastest_from_bytes": next((r["bytes_per_replica"] for r in own if r["fastest"] == "host_all_cores"), None),

@@ -193,7 +193,9 @@ int ftv_vote_mem(ftv_ctx *ctx, const ftv_vote_desc *desc, const int32_t *memory,
  * and GPU -- because which one is fastest depends on the data size (Sec. V-A,
  * Fig. 3).  Every pointer in `desc` is HOST memory (replicas, consensus,
  * mask, stats).  threads = 1: the calling thread only; 0: one thread per core
- * the process may use; otherwise that many threads (OpenMP).  Results are
+ * the process may use; otherwise that many threads (OpenMP); in every case at
+ * most one thread per 4096 elements, so a small vote runs on the calling
+ * thread without a parallel region.  Results are
  * bit-identical to ftv_vote on the same replicas.  Synchronous: outputs are
  * complete when the call returns.  Needs no GPU.  Errors: FTV_E_INVALID,
  * FTV_E_DTYPE, FTV_E_K, FTV_E_ALIGN (a pointer not a multiple of the element

@@ -215,9 +215,18 @@ void host_finish(const HCounts &c, uint32_t k, uint64_t n, ftv_stats *st) {
   }
 }
 
+// Elements per thread at least: a thread then votes for about 6 us (4096 fp32
+// elements of k = 3 on one core), more than the fork and join of the team;
+// with fewer, a team of one thread per core costs more than it saves and is
+// exposed to the scheduler time slices of the process's other threads (a
+// 16 KiB vote on 16 threads once measured about 1 ms, against 6 us on one).
+constexpr uint64_t kMinPerThread = 4096;
+
 template <int DT, int TOL, int K>
 void host_vote_k(const ftv_vote_desc &d, const HTol &t, int threads, HCounts &total) {
   memset(&total, 0, sizeof(total));
+  const uint64_t most = (d.n + kMinPerThread - 1) / kMinPerThread;
+  if ((uint64_t)threads > most) threads = (int)most;
   if (threads <= 1 || d.n < 2) {
     host_range<DT, TOL, K>(d, t, 0, d.n, total);
     return;
