@@ -4,8 +4,8 @@
 // A grid-stride loop over tiles of 16-byte vectors; each workgroup reduces its
 // wave accumulators and adds the non-zero totals to the launch's device
 // accumulators (most workgroups see no disagreement and add nothing).  The
-// kernel runs one workgroup per CU, so registers are plentiful: up to k = 5
-// counts go to per-lane counters and the general vote of an element with
+// kernel runs one workgroup per CU, so registers are plentiful: counts go to
+// per-lane counters and, up to k = 5, the general vote of an element with
 // several differing values runs in place from the loaded registers.  A
 // one-workgroup finalize kernel on the same stream then decides the verdict,
 // writes the stats record and clears the accumulators: the kernel boundary
@@ -17,8 +17,6 @@
 // loaded from one code object holding every vote kernel (about 1 MB of code)
 // than from a small one.
 #pragma once
-
-#include <type_traits>
 
 #include "ftv_internal.hpp"
 #include "ftv_vote_dev.hpp"
@@ -79,17 +77,19 @@ struct TaskShape {
   static constexpr bool lean = s.lean;
 };
 
-// In-place general votes and per-lane counts up to k = 5.  From k = 6 on the
-// tolerance tests of an in-place general vote (15 or 21 lane masks) and the
-// counts overflow the scalar registers, which the compiler then spills
-// through lanes of a vector register: for the fp32 16384^2 task the kernel
-// measured 1.86 ms at k = 7 that way against 1.64-1.67 ms with the
-// element-by-element loop, ballot counts and the fix-up pass, and 1.48 ms
-// against 1.45 ms at k = 6, so k = 6 and 7 keep that loop.
+// Counts in per-lane counters at every k; the general vote in place up to
+// k = 5.  From k = 6 on the tolerance tests of an in-place general vote (15
+// or 21 lane masks) overflow the scalar registers, which the compiler then
+// spills through lanes of a vector register: for the fp32 16384^2 task the
+// kernel measured 1.86 ms at k = 7 that way against 1.62-1.67 ms with the
+// element-by-element loop and the fix-up pass, and 1.48 ms against 1.45 ms at
+// k = 6, so k = 6 and 7 keep that loop.  There the per-lane counters also
+// free the 58 scalar registers of 64-bit ballot counts (k = 7: 90 spilled
+// scalars with ballot counts, none with per-lane ones; 1.66 -> 1.62 ms).
 template <int K>
 struct TaskAcc {
   static constexpr bool inl = K <= 5;
-  using type = typename std::conditional<(K <= 5), LaneAcc<K>, Acc<K>>::type;
+  using type = LaneAcc<K>;
 };
 
 template <int DT, int TOL, int K, bool VEC>
