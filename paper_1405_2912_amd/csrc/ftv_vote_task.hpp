@@ -34,11 +34,12 @@ using namespace dev;
 // replica): for k = 3 fp32, 256 threads with four vectors in flight per lane
 // and replica streamed at 0.76 ms against 0.79 ms for 512 threads with two.
 // Full tiles go through the branch-free step of vote_step_full; where the
-// sweep found the general step as fast (k = 3 and 6 with 8-byte elements)
-// every tile uses vote_range.  Re-swept once counts moved to per-lane
-// counters and general votes into the registers: k = 4 (256 threads, U = 2:
-// fp32 0.946 against 0.952 ms, fp64 8192^2 0.433 against 0.458 ms) and fp32
-// k = 6 (U = 4: 1.408 against 1.441 ms) changed; the other entries held.  Bit-wise (EXACT) votes keep 512
+// sweep found the general step as fast (k = 3 with 8-byte elements) every
+// tile uses vote_range.  Re-swept once counts moved to per-lane counters and
+// general votes into the registers: k = 4 (256 threads, U = 2: fp32 0.946
+// against 0.952 ms, fp64 8192^2 0.433 against 0.458 ms) and k = 6 (256
+// threads, U = 4: fp32 1.408 against 1.441 ms, fp64 0.668 against 0.741 ms)
+// changed; the other entries held.  Bit-wise (EXACT) votes keep 512
 // threads and the general step: their cheaper compare measured faster that way
 // (k = 3 int32: 0.74 ms against 0.80 ms).  More workgroups per CU measured
 // slower throughout: longer contiguous steps and fewer concurrent streams keep
@@ -65,7 +66,7 @@ constexpr VoteShape vote_shape(int es, int tol, int k) {
     case 3: return {512, 2, false};
     case 4: return {256, 2, true};
     case 5: return {512, 2, true};
-    case 6: return {512, 1, false};
+    case 6: return {256, 4, true};
     default: return {256, 1, true};
   }
 }
