@@ -39,9 +39,11 @@ using namespace dev;
 // general votes into the registers: k = 4 (256 threads, U = 2: fp32 0.946
 // against 0.952 ms, fp64 8192^2 0.433 against 0.458 ms) and k = 6 (256
 // threads, U = 4: fp32 1.408 against 1.441 ms, fp64 0.668 against 0.741 ms)
-// changed; the other entries held.  Bit-wise (EXACT) votes keep 512
-// threads and the general step: their cheaper compare measured faster that way
-// (k = 3 int32: 0.74 ms against 0.80 ms).  More workgroups per CU measured
+// changed; the other entries held.  Bit-wise (EXACT) votes of 8-byte
+// elements keep 512 threads and the general step (k = 3 int32 once measured
+// 0.74 ms that way against 0.80 ms); for 4-byte elements the re-sweep found
+// 256 threads better up to k = 4 (int32 k = 3, U = 2: 0.762 against 0.787 ms;
+// k = 2, U = 4: 0.593 against 0.601 ms).  More workgroups per CU measured
 // slower throughout: longer contiguous steps and fewer concurrent streams keep
 // DRAM page locality, and a grid larger than what is resident leaves a tail.
 struct VoteShape {
@@ -50,6 +52,14 @@ struct VoteShape {
   bool lean;
 };
 constexpr VoteShape vote_shape(int es, int tol, int k) {
+  if (tol == FTV_TOL_EXACT && es == 4) {
+    switch (k) {
+      case 2: return {256, 4, true};
+      case 3: return {256, 2, true};
+      case 4: return {256, 2, true};
+      default: return {512, 1, false};
+    }
+  }
   if (tol == FTV_TOL_EXACT) return {512, k <= 3 ? 2 : 1, false};
   if (es == 4) {
     switch (k) {
