@@ -445,13 +445,13 @@ int ftv_record_vote(ftv_unit *units, uint32_t nunits, const uint32_t *unit_of_re
 
 /* ---- memory areas with siblings and versions (Sec. IV-A, IV-C) ------------ *
  * The runtime's memory management: a registered area has copies ("siblings")
- * in host memory and in device memory, each tagged with a version that is
- * increased by one on write access.  A request for the area in some memory
+ * in host memory and in device memory, each tagged with a version that every
+ * write raises by one.  A request for the area in some memory
  * returns a sibling there holding the highest version, copying the data into
  * a new (or stale, reused) sibling when that memory has none.  In
  * fault-tolerant mode a request is only served by an existing sibling when
- * another highest-version sibling exists as well; otherwise a new sibling is
- * created and returned, so the previous one survives as the backup.  A kernel
+ * another highest-version sibling exists as well; otherwise the request gets a
+ * fresh sibling, so the previous one survives as the backup.  A kernel
  * that ran into a fault releases its sibling with ok = 0, which invalidates
  * it; the next request copies from a valid sibling (Fig. 1).  ftv_mm_check
  * compares the highest-version siblings by block fingerprints and invalidates
@@ -550,15 +550,15 @@ int ftv_mm_check(ftv_mm *mm, uint32_t area, uint64_t block_bytes, void *stream,
  * everywhere, and the runtime of a valid run's unit becomes the running mean
  * of its valid runs' GPU times.  An UNRESOLVED vote changes no profile and
  * starts the next attempt, re-ranked; fewer than two implementations left
- * end the call.  Check intervals (Sec. IV-B: a unit with p = 1 is only used
- * in predefined check intervals): when cfg->check_interval > 0, each attempt
+ * end the call.  Check intervals (Sec. IV-B: a unit with p = 1 is tried again only
+ * at fixed intervals): when cfg->check_interval > 0, each attempt
  * passes over the units with F = +infinity that are not among its k runs,
  * adding 1 to their `skipped`; the first (in rank order) whose count would
  * reach check_interval instead runs as an extra replica of the attempt
  * (k + 1 runs, at most FTV_MAX_K) and is voted and counted like the others,
  * so a unit that has recovered regains a finite F; a unit that runs has its
- * count reset to 0.  Readings: the paper restarts with "the next best
- * combination" after a fault and votes DMR pairs; the exclusion rule, the
+ * count reset to 0.  Readings: after a fault the paper moves on to the
+ * best-ranked remaining pairing of kernel and unit and votes DMR pairs; the exclusion rule, the
  * running mean, counting a failed run as an invalid one and re-trying as an
  * extra replica are this library's. */
 typedef int (*ftv_task_fn)(void *user, void *out, void *stream);

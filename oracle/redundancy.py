@@ -13,7 +13,8 @@ What the paper fixes:
   * a task is duplicated onto the combinations with the lowest fault-aware
     runtime and the voter decides which result is taken as correct;
   * a run that reports a direct fault (an API error) is abandoned, its data
-    invalid, and execution restarts with the next best combination;
+    invalid, and the task goes on with the best-ranked remaining pairing
+    of kernel and unit;
   * a run that does not finish within its profiled runtime times a
     user-defined factor is abandoned the same way.
 
@@ -30,8 +31,8 @@ Readings where the paper is silent (the library's):
     attempt re-ranks;
   * a timeout applies only to a unit with a profile (R > 0 and v > 0); its
     limit is R * factor;
-  * check intervals (the paper: a unit with p = 1 is only used in predefined
-    check intervals): with an interval N > 0, each attempt passes over the
+  * check intervals (Sec. IV-B: a unit with p = 1 is tried again only at
+    fixed intervals): with an interval N > 0, each attempt passes over the
     units with F = inf outside its k best runs and counts one more skip for
     each; the first such unit (in rank order) whose count would reach N runs
     instead as an extra replica of the attempt, voted and counted like the

@@ -8,15 +8,14 @@ shares no code with the library.
 
 What the paper fixes:
   * a registered area has copies ("siblings") in one or more memories, each
-    tagged with a version that is increased by one on write access;
-  * a request for an area in some memory looks for the sibling with the
-    highest version; if that memory holds one, its address is returned,
-    otherwise a new sibling is created there and the data copied from a
-    highest-version sibling;
+    tagged with a version that every write raises by one;
+  * a request for an area in some memory looks for the newest version; if
+    that memory holds a sibling at it, that sibling's address comes back,
+    otherwise a sibling is made there and filled from a newest-version one;
   * fault-tolerant mode: if the desired memory holds a highest-version sibling
-    and another highest-version sibling exists anywhere, the one in the desired
-    memory is used; if only one highest-version sibling exists, a new sibling is
-    created and returned, so that the old one survives as the backup;
+    and another highest-version sibling exists anywhere, the request gets the
+    one in its own memory; if the newest version has a single sibling, the
+    request gets a fresh one, so that the old one survives as the backup;
   * a fault detected during the kernel marks the sibling it used invalid; the
     next request copies from another valid sibling.
 

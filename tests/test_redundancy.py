@@ -34,8 +34,8 @@ def test_dmr_on_the_two_best_units():
 
 
 def test_direct_fault_restarts_on_the_next_best():
-    """Sec. IV-C: a run that reports an API error is abandoned and execution
-    restarts with the next best combination."""
+    """Sec. IV-C: a run that reports an API error is abandoned and the task goes
+    on with the best-ranked remaining pairing of kernel and unit."""
     good = _vals(2)
     units = [Unit(1.0), Unit(2.0), Unit(3.0)]
     beh = {0: (ERROR, None, 0.0), 1: (OK, good, 2.0), 2: (OK, good, 3.0)}

@@ -50,7 +50,7 @@ def test_fig1_fault_on_the_device_and_restart():
 def test_normal_mode_reuses_the_sibling_in_place():
     """Sec. IV-A: a request returns the address of an up-to-date sibling that
     is already in the memory; a write raises the version by one; a request
-    elsewhere transfers from the sibling with the highest version."""
+    elsewhere copies from the newest-version sibling."""
     m = Manager(fault_tolerant=False)
     a = m.register(_data(4))
     s = m.request(a, HOST, READWRITE)
@@ -71,7 +71,7 @@ def test_normal_mode_reuses_the_sibling_in_place():
 
 def test_fault_tolerant_mode_keeps_a_backup():
     """Sec. IV-A: with only one highest-version sibling a new one is created
-    even in the same memory; with two, the one in the desired memory is used."""
+    even in the same memory; with two, the request gets the one in its memory."""
     m = Manager(fault_tolerant=True)
     a = m.register(_data(7))
     s = m.request(a, HOST, WRITE)      # only one newest copy: a new host sibling
