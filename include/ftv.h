@@ -144,7 +144,13 @@ int ftv_ctx_destroy(ftv_ctx *ctx);
  * no_majority = #(mask bit 7).  Verdict from those counts (see FTV_* above).
  * Results are bit-exact functions of the inputs: no launch shape, tile size or
  * schedule changes them.
- * Errors: FTV_E_INVALID (NULL replica/stats, reserved != 0, bad tolerance),
+ * No output (consensus, mask, stats) may share a byte with a replica or with
+ * another output (FTV_E_INVALID): the general vote of an element may read its
+ * replicas again after outputs of the same launch are stored, so the
+ * consensus cannot be written over a replica.  Replicas may overlap each
+ * other.
+ * Errors: FTV_E_INVALID (NULL replica/stats, reserved != 0, bad tolerance,
+ * overlapping outputs, n above 2^60),
  * FTV_E_DTYPE, FTV_E_K, FTV_E_ALIGN (pointer not a multiple of the element
  * size; stats not 8-byte aligned), FTV_E_BUSY (a 65th stream on the context),
  * FTV_E_HIP. */
@@ -196,8 +202,8 @@ int ftv_vote_mem(ftv_ctx *ctx, const ftv_vote_desc *desc, const int32_t *memory,
  * the process may use; otherwise that many threads (OpenMP); in every case at
  * most one thread per 4096 elements, so a small vote runs on the calling
  * thread without a parallel region.  Results are
- * bit-identical to ftv_vote on the same replicas.  Synchronous: outputs are
- * complete when the call returns.  Needs no GPU.  Errors: FTV_E_INVALID,
+ * bit-identical to ftv_vote on the same replicas, under the same overlap
+ * rule.  Synchronous: outputs are complete when the call returns.  Needs no GPU.  Errors: FTV_E_INVALID,
  * FTV_E_DTYPE, FTV_E_K, FTV_E_ALIGN (a pointer not a multiple of the element
  * size; stats not 8-byte aligned). */
 int ftv_vote_host(const ftv_vote_desc *desc, uint32_t threads);
@@ -206,7 +212,9 @@ int ftv_vote_host(const ftv_vote_desc *desc, uint32_t threads);
  * tolerances) in ONE persistent kernel launch, replayed from a captured HIP
  * graph (the small-task motivation: Sec. V-A, the voter's best device depends
  * on the data size).  `descs` is a HOST array.  Each task's results are
- * identical to those of ftv_vote on the same task.  Additional requirement:
+ * identical to those of ftv_vote on the same task.  Tasks of one call run
+ * concurrently: no task may write memory that another
+ * task of the call reads or writes (not checked).  Additional requirement:
  * every replica and consensus pointer 16-byte aligned and every mask pointer
  * 4-byte aligned (FTV_E_ALIGN otherwise).  The host arrays may be reused as
  * soon as the call returns.  Errors: those of ftv_vote for the first invalid
@@ -309,9 +317,11 @@ typedef struct ftv_block_stats {
  * blockmap: nblocks bytes: bit r = replica r's fingerprint differs from the
  * source's, bit 7 = no fingerprint majority.  consensus: nbytes, 16-byte
  * aligned.  mask: n bytes (4-byte aligned) or NULL; 0 outside fallback blocks,
- * element-vote mask inside them.  bstats: device, 8-byte aligned.
+ * element-vote mask inside them.  bstats: device, 8-byte aligned.  No output
+ * may share a byte with a replica or another output (the restore copies
+ * whole blocks while blocks of every replica are still read).
  * Errors: FTV_E_INVALID (NULL argument, block size, nbytes not a multiple of
- * the element size, more than 2^31 - 1 blocks), FTV_E_K, FTV_E_DTYPE (also an
+ * the element size, more than 2^31 - 1 blocks, overlapping outputs), FTV_E_K, FTV_E_DTYPE (also an
  * illegal fallback tolerance), FTV_E_ALIGN, FTV_E_NOMEM (fingerprint
  * workspace), FTV_E_HIP. */
 int ftv_vote_blocks(ftv_ctx *ctx, const void *const *replicas, uint32_t k, int32_t dtype,

@@ -57,6 +57,36 @@ TolD to_tol_d(int dtype, const ftv_tol &t) {
   return d;
 }
 
+bool spans_meet(const Span &a, const Span &b) {
+  if (!a.p || !b.p || !a.len || !b.len) return false;
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a.p), y = reinterpret_cast<uintptr_t>(b.p);
+  return x < y + b.len && y < x + a.len;
+}
+
+// The outputs of one launch share no byte with its inputs or with each other:
+// the kernels read replica elements again after some outputs of the same
+// launch are stored (the fix-up pass of the general vote, the block restore),
+// and outputs written by different lanes would race.  Input ranges may
+// overlap (read only).
+int check_disjoint(const Span *outs, int nouts, const Span *ins, int nins) {
+  for (int o = 0; o < nouts; ++o) {
+    for (int r = 0; r < nins; ++r)
+      if (spans_meet(outs[o], ins[r])) return fail(FTV_E_INVALID, "an output overlaps a replica");
+    for (int q = o + 1; q < nouts; ++q)
+      if (spans_meet(outs[o], outs[q])) return fail(FTV_E_INVALID, "two outputs overlap");
+  }
+  return FTV_OK;
+}
+
+int check_vote_overlaps(const ftv_vote_desc *d) {
+  if (d->n > (UINT64_MAX >> 4)) return fail(FTV_E_INVALID, "n too large");
+  const uint64_t nb = d->n * (uint64_t)elem_size(d->dtype);
+  const Span outs[3] = {{d->consensus, nb}, {d->mask, d->n}, {d->stats, sizeof(ftv_stats)}};
+  Span ins[FTV_MAX_K];
+  for (uint32_t r = 0; r < d->k; ++r) ins[r] = {d->replicas[r], nb};
+  return check_disjoint(outs, 3, ins, (int)d->k);
+}
+
 // Validate a vote descriptor and fill the device task record.  strict = batch
 // alignment rules (16-byte replicas/consensus, 4-byte mask).
 int make_task(const ftv_vote_desc *d, bool strict, TaskD *out) {
@@ -80,6 +110,8 @@ int make_task(const ftv_vote_desc *d, bool strict, TaskD *out) {
   if (d->mask) vec = vec && aligned(d->mask, 4);
   if (strict && !vec)
     return fail(FTV_E_ALIGN, "batched tasks need 16-byte aligned replicas/consensus, 4-byte mask");
+  rc = check_vote_overlaps(d);
+  if (rc) return rc;
   memset(out, 0, sizeof(*out));
   for (uint32_t r = 0; r < d->k; ++r) out->rep[r] = d->replicas[r];
   out->cons = d->consensus;
@@ -908,6 +940,17 @@ int ftv_vote_blocks(ftv_ctx *c, const void *const *replicas, uint32_t k, int32_t
     if ((uintptr_t)consensus % 16) return fail(FTV_E_ALIGN, "consensus must be 16-byte aligned");
     if (mask && (uintptr_t)mask % 4) return fail(FTV_E_ALIGN, "mask must be 4-byte aligned");
     if (fps && (uintptr_t)fps % 8) return fail(FTV_E_ALIGN, "fps must be 8-byte aligned");
+  }
+  {
+    // no output may touch a replica or another output: pass 1 streams
+    // replica 0 into the consensus while pass 2 still reads every replica of
+    // the blocks that need the element vote
+    const Span outs[5] = {{consensus, nbytes}, {mask, nbytes / es}, {blockmap, nblocks},
+                          {fps, fps ? (uint64_t)k * nblocks * 8 : 0}, {bstats, sizeof(ftv_block_stats)}};
+    Span ins[FTV_MAX_K];
+    for (uint32_t r = 0; r < k; ++r) ins[r] = {replicas[r], nbytes};
+    rc = check_disjoint(outs, 5, ins, (int)k);
+    if (rc) return rc;
   }
   BlockVoteD b;
   memset(&b, 0, sizeof(b));

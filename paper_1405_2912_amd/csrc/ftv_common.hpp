@@ -24,6 +24,18 @@ TolD to_tol_d(int dtype, const ftv_tol &t);
 // alignment rules.
 int make_task(const ftv_vote_desc *d, bool strict, TaskD *out);
 
+// [p, p + len) as a byte range; a NULL pointer or zero length is empty.
+struct Span {
+  const void *p;
+  uint64_t len;
+};
+// FTV_E_INVALID if an output range shares a byte with an input range or with
+// another output range (inputs may overlap each other).
+int check_disjoint(const Span *outs, int nouts, const Span *ins, int nins);
+// The overlap rule of one vote descriptor: consensus, mask and stats against
+// the replicas and each other.  Also rejects n above 2^60.
+int check_vote_overlaps(const ftv_vote_desc *d);
+
 // State of ftv_run_redundant kept in a context (abandoned replicas); freed
 // with the context after the device has been synchronised.
 struct RunState;

@@ -293,6 +293,8 @@ int ftv_vote_host(const ftv_vote_desc *d, uint32_t threads) {
     if ((uintptr_t)d->replicas[r] % es) return fail(FTV_E_ALIGN, "replica not element-aligned");
   }
   if (d->consensus && (uintptr_t)d->consensus % es) return fail(FTV_E_ALIGN, "consensus not element-aligned");
+  rc = check_vote_overlaps(d);  // the same rule as the device voter's
+  if (rc) return rc;
   const TolD td = to_tol_d(d->dtype, d->tol);
   const HTol t{td.max_ulp, td.delta, td.abs_floor};
   const int T = host_threads(threads);

@@ -712,9 +712,11 @@ def _stats_dict(s: Stats) -> dict:
             "n": int(s.n), "verdict": int(s.verdict), "winner": int(s.winner)}
 
 
-def vote_host(replicas, tol: Tol, threads: int = 1, want_consensus: bool = True, want_mask: bool = True):
+def vote_host(replicas, tol: Tol, threads: int = 1, want_consensus: bool = True, want_mask: bool = True,
+              consensus=None, mask=None):
     """ftv_vote_host on k C-contiguous numpy arrays of one dtype (host memory);
-    returns (consensus, mask, stats dict).  threads: 1 = one thread, 0 = every core."""
+    returns (consensus, mask, stats dict).  threads: 1 = one thread, 0 = every core.
+    consensus / mask: caller arrays to write; otherwise new arrays when wanted."""
     if not 1 <= len(replicas) <= MAX_K:
         _bad(f"1 to {MAX_K} replicas")
     x0 = replicas[0]
@@ -728,8 +730,12 @@ def vote_host(replicas, tol: Tol, threads: int = 1, want_consensus: bool = True,
             _bad(f"replica {r} must be a C-contiguous numpy array")
         if a.dtype != x0.dtype or a.size < n:
             _bad(f"replica {r} must have dtype {x0.dtype} and at least {n} elements")
-    cons = np.empty(n, dtype=x0.dtype) if want_consensus else None
-    mask = np.empty(n, dtype=np.uint8) if want_mask else None
+    for name, a, dt in (("consensus", consensus, x0.dtype), ("mask", mask, np.dtype(np.uint8))):
+        if a is not None and (not isinstance(a, np.ndarray) or not a.flags["C_CONTIGUOUS"] or a.dtype != dt
+                              or a.size < n or not a.flags["WRITEABLE"]):
+            _bad(f"{name} must be a writeable C-contiguous numpy array of {dt} with at least {n} elements")
+    cons = consensus if consensus is not None else (np.empty(n, dtype=x0.dtype) if want_consensus else None)
+    mask = mask if mask is not None else (np.empty(n, dtype=np.uint8) if want_mask else None)
     st = Stats()
     d = VoteDesc()
     for r, a in enumerate(replicas):

@@ -172,3 +172,29 @@ def test_host_voter_errors(ftv):
     with pytest.raises(ftv.FtvError) as e:
         ftv.vote_host(reps[:1], ftv.ulp(4))
     assert e.value.code == ftv.E_K
+
+
+def test_host_voter_overlaps_rejected(ftv):
+    """Outputs share no byte with a replica or with each other (the same rule
+    as the device voter's); replicas may overlap each other."""
+    n = 1000
+    buf = np.zeros(3 * n + 8, dtype=np.float32)
+    a, b, c = buf[:n], buf[n:2 * n], buf[2 * n:3 * n]
+    spare = np.zeros(n + 4, dtype=np.float32)
+    cases = {
+        "consensus is replica 0": dict(consensus=a),
+        "consensus is replica 1": dict(consensus=b),
+        "consensus shifted into replica 0": dict(consensus=buf[1:n + 1]),
+        "consensus runs into replica 2": dict(consensus=buf[2 * n - 4:3 * n - 4]),
+        "mask inside replica 1": dict(consensus=spare[:n], mask=b.view(np.uint8)[:n]),
+        "mask inside the consensus": dict(consensus=spare[:n], mask=spare.view(np.uint8)[:n]),
+    }
+    for where, kw in cases.items():
+        with pytest.raises(ftv.FtvError) as e:
+            ftv.vote_host([a, b, c], ftv.ulp(1), **kw)
+        assert e.value.code == ftv.E_INVALID, where
+    assert not buf.any() and not spare.any()      # nothing was written
+    buf[:] = np.arange(buf.size, dtype=np.float32)
+    cons, _, s = ftv.vote_host([a, a, buf[1:n + 1]], ftv.ulp(0), consensus=spare[:n])
+    assert s["verdict"] == ftv.TASK_MAJORITY and s["disagree"][2] == n
+    assert np.array_equal(cons[:n], a)
