@@ -404,8 +404,11 @@ typedef struct ftv_server_stats {
  * handle.  Errors: FTV_E_INVALID (NULL argument, a field out of range,
  * reserved != 0), FTV_E_NOMEM (arena or tables), FTV_E_HIP. */
 int ftv_server_create(const ftv_server_cfg *cfg, ftv_server **out);
-/* Enqueue a request; *ticket identifies it.  FTV_E_NOMEM if its footprint
- * alone exceeds the budget, FTV_E_BUSY if the queue is full. */
+/* Enqueue a request; *ticket identifies it.  A vote request's descriptor
+ * follows ftv_vote's rules (FTV_E_INVALID, FTV_E_ALIGN, ... as there);
+ * requests in flight together share launches, so no request may write memory
+ * that another one in flight reads or writes (not checked).  FTV_E_NOMEM if
+ * its footprint alone exceeds the budget, FTV_E_BUSY if the queue is full. */
 int ftv_submit(ftv_server *srv, const ftv_request *req, uint64_t *ticket);
 /* Wait up to wait_us (0 = do not wait, <0 = forever) for a ticket.
  * FTV_OK with *out filled, FTV_E_NOTREADY, or FTV_E_CLOSED (unknown ticket). */

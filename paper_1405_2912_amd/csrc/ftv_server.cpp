@@ -232,13 +232,26 @@ void admit(ftv_server *s) {
         r.mask = d.mask;
       }
       const int slot = s->free_slots.back();
-      s->free_slots.pop_back();
-      r.slot = slot;
       d.consensus = r.cons;
       d.mask = r.mask;
       d.stats = s->d_stats + slot;
       TaskD t;
-      (void)make_task(&d, true, &t);  // validated by ftv_submit
+      const int trc = make_task(&d, true, &t);
+      if (trc != FTV_OK) {
+        // validated at submission with the caller's outputs; only the
+        // server's own placement could fail here: end the request with the
+        // error instead of launching it
+        free_outputs(s, r);
+        r.state = Q_DONE;
+        r.status = trc;
+        r.t_done = now;
+        note_queue(s, now);
+        s->queue.pop_front();
+        s->cv_done.notify_all();
+        continue;
+      }
+      s->free_slots.pop_back();
+      r.slot = slot;
       r.nvec = t.nvec;
       r.tile_vecs = request_tile_vecs(t.nvec, s->num_cus);
       r.ntiles = (uint32_t)std::max<uint64_t>(1, (t.nvec + r.tile_vecs - 1) / r.tile_vecs);
