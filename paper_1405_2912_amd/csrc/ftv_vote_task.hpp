@@ -46,15 +46,26 @@ using namespace dev;
 // k = 2, U = 4: 0.593 against 0.601 ms).  More workgroups per CU measured
 // slower throughout: longer contiguous steps and fewer concurrent streams keep
 // DRAM page locality, and a grid larger than what is resident leaves a tail.
+//
+// xcd: the full tiles of one grid-stride round are handed out so that the
+// workgroups of one XCD (the hardware deals workgroups out to the 8 XCDs
+// round robin) take adjacent tiles, each XCD streaming one contiguous eighth
+// of the round instead of every eighth tile.  Measured against the plain
+// order on the 1 GiB / 512 MiB replicas: fp32 k = 3 0.727 against 0.740 ms,
+// k = 2 0.576-0.581 against 0.582; int32 bit-wise k = 2 0.585 against
+// 0.591-0.595; fp64 k = 7 0.738 against 0.752 ms, k = 4 0.422 against
+// 0.424-0.428 ms; but fp32 k = 5 1.20-1.22 against 1.13 ms and k = 4 0.954
+// against 0.942 ms, and no change elsewhere, so only those shapes use it.
 struct VoteShape {
   int threads;
   int unroll;
   bool lean;
+  bool xcd = false;
 };
 constexpr VoteShape vote_shape(int es, int tol, int k) {
   if (tol == FTV_TOL_EXACT && es == 4) {
     switch (k) {
-      case 2: return {256, 4, true};
+      case 2: return {256, 4, true, true};
       case 3: return {256, 2, true};
       case 4: return {256, 2, true};
       default: return {512, 1, false};
@@ -63,8 +74,8 @@ constexpr VoteShape vote_shape(int es, int tol, int k) {
   if (tol == FTV_TOL_EXACT) return {512, k <= 3 ? 2 : 1, false};
   if (es == 4) {
     switch (k) {
-      case 2: return {256, 4, true};
-      case 3: return {256, 4, true};
+      case 2: return {256, 4, true, true};
+      case 3: return {256, 4, true, true};
       case 4: return {256, 2, true};
       case 5: return {256, 2, true};
       case 6: return {256, 4, true};
@@ -74,10 +85,10 @@ constexpr VoteShape vote_shape(int es, int tol, int k) {
   switch (k) {
     case 2: return {256, 4, true};
     case 3: return {512, 2, false};
-    case 4: return {256, 2, true};
+    case 4: return {256, 2, true, true};
     case 5: return {512, 2, true};
     case 6: return {256, 4, true};
-    default: return {256, 1, true};
+    default: return {256, 1, true, true};
   }
 }
 constexpr int kVoteWgPerCu = 1;
@@ -89,6 +100,7 @@ struct TaskShape {
   static constexpr int threads = s.threads;
   static constexpr int U = s.unroll;
   static constexpr bool lean = s.lean;
+  static constexpr bool xcd = s.xcd;
 };
 
 // Counts in per-lane counters at every k; the general vote in place up to
@@ -120,7 +132,9 @@ __global__ __launch_bounds__((TaskShape<DT, TOL, K, VEC>::threads)) void k_vote_
   if constexpr (S::lean) {
     // full tiles grid-stride, then the partial tile (if any) by its owner
     const uint64_t nfull = t.nvec / tile;
-    for (uint64_t i = blockIdx.x; i < nfull; i += gridDim.x) vote_step_full<DT, TOL, K, U, INL>(t, i * tile, acc);
+    const uint32_t g = gridDim.x;
+    const uint32_t first = (S::xcd && g % 8u == 0u) ? (blockIdx.x % 8u) * (g / 8u) + blockIdx.x / 8u : blockIdx.x;
+    for (uint64_t i = first; i < nfull; i += g) vote_step_full<DT, TOL, K, U, INL>(t, i * tile, acc);
     if (nfull * tile < t.nvec && blockIdx.x == nfull % gridDim.x)
       vote_range<DT, TOL, K, VEC, U, INL>(t, nfull * tile, t.nvec, acc, true);
   } else {

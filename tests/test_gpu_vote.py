@@ -165,6 +165,24 @@ def test_full_steps_and_optional_outputs(gpu, ctx, dtype, k):
             _check(_run(gpu, ctx, reps, tol_f, want_cons=wc, want_mask=wm), ref, k, where)
 
 
+@pytest.mark.parametrize("dtype,k,tile_elems,exact", [(np.float32, 2, 4096, False), (np.float32, 3, 4096, False),
+                                                      (np.int32, 2, 4096, True), (np.float64, 4, 1024, False),
+                                                      (np.float64, 7, 512, False)])
+def test_xcd_tile_order_many_rounds(gpu, ctx, dtype, k, tile_elems, exact):
+    """The launch shapes that hand out a round's tiles XCD by XCD, with the
+    full grid of one workgroup per CU, two and a half grid-stride rounds, a
+    partial tile and a ragged tail: every element is voted once."""
+    rng = np.random.default_rng(700 + k)
+    n = 5 * 128 * tile_elems + tile_elems // 2 + 3
+    reps = _replicas(rng, dtype, k, n)
+    m = 4 if dtype == np.float32 else 2
+    tols = [(oracle.exact(), gpu.exact())] if exact else [(oracle.ulp(m), gpu.ulp(m)), (oracle.rel(1e-3), gpu.rel(1e-3))]
+    for tol_o, tol_f in tols:
+        where = f"xcd order {np.dtype(dtype).name} k={k} n={n} tol={tol_o}"
+        print("case:", where, flush=True)
+        _check(_run(gpu, ctx, reps, tol_f), oracle.vote(reps, tol_o), k, where)
+
+
 def test_repeat_is_deterministic(gpu, ctx):
     reps = synth.small_task_set(n=300001)
     a = _run(gpu, ctx, reps, gpu.ulp(4))
