@@ -117,6 +117,35 @@ def test_block_vote_replica0_outlier(gpu, k):
         assert ref.replica_blocks[0] >= 3 and ref.fallback_blocks >= 1
 
 
+def test_xcd_block_order_many_runs(gpu, ctx):
+    """More whole blocks than two runs of the XCD block order (8 x 64 blocks
+    per run) plus a partial run and a ragged last block: every block is
+    hashed once, in the fingerprints and in the block vote (replica 0 outvoted
+    in blocks of different runs, one block without a fingerprint majority)."""
+    import torch
+    rng = np.random.default_rng(2024)
+    bb = 4096
+    nwhole = 2 * 512 + 37
+    raw = rng.integers(0, 256, nwhole * bb + 1000, dtype=np.uint8)
+    print(f"case: fingerprint of {nwhole} whole blocks + a partial one", flush=True)
+    fp = gpu.fingerprint(ctx, torch.from_numpy(raw).cuda(), bb)
+    torch.cuda.synchronize()
+    assert np.array_equal(fp.cpu().numpy().view(np.uint64), oracle.fingerprint(raw, bb))
+    per = bb // 8
+    n = nwhole * per + 100
+    base = synth.values("f64", synth.NORMAL, 17, 0, n)
+    reps = [base.copy() for _ in range(5)]
+    for blk in (3, 511, 512, 700, 1030, nwhole):        # replica 0 outvoted (the last: the partial block)
+        reps[0].view(np.uint64)[min(n - 1, blk * per + 5)] ^= 2
+    for r in range(1, 5):                               # block 600: no fingerprint majority
+        reps[r].view(np.uint64)[600 * per + r] ^= 1
+    for r, blk in ((2, 100), (3, 513), (4, 1060)):
+        reps[r].view(np.uint64)[blk * per + 11] ^= 8
+    print(f"case: block vote k=5 fp64 over {nwhole} whole blocks + a partial one", flush=True)
+    ref = _block_case(gpu, reps, oracle.ulp(0), gpu.ulp(0), bb)
+    assert ref.replica_blocks[0] == 6 and ref.fallback_blocks == 1
+
+
 def test_block_vote_empty_and_tiny(gpu):
     for n in (0, 1, 5):
         reps = [np.arange(n, dtype=np.float64) for _ in range(3)]
